@@ -1,0 +1,88 @@
+"""FP64 dense steps of LOBPCG (test infrastructure; see the package docstring).
+
+Cholesky QR (paper Section 3.5):  B = W^T W,  B = R^T R,  W <- W R^{-1}.
+Gram blocks (eq. Glower): only the lower blocks of G = S^T H S and
+O = S^T S are formed; each upper block is the transpose of its lower
+counterpart, and each diagonal block is averaged with its own transpose.
+Rayleigh-Ritz (eq. rreig): the pencil (G, O) is reduced with the Cholesky
+factor of O and solved by a symmetric eigensolver; the k leftmost Ritz pairs
+are kept, in ascending order (the paper calls LAPACK dsygv, which does the same
+reduction).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+class NotSPD(np.linalg.LinAlgError):
+    pass
+
+
+def gram(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """A^T B in FP64 (inputs upcast exactly)."""
+    return np.asarray(A, dtype=np.float64).T @ np.asarray(B, dtype=np.float64)
+
+
+def cholesky_upper(B: np.ndarray) -> np.ndarray:
+    """R upper triangular with B = R^T R; raises NotSPD if B is not positive definite."""
+    try:
+        L = np.linalg.cholesky(B)
+    except np.linalg.LinAlgError as e:
+        raise NotSPD(str(e)) from None
+    if not np.all(np.isfinite(L)) or np.any(np.diag(L) <= 0):
+        raise NotSPD("non-positive pivot")
+    return L.T.copy()
+
+
+def cholqr(W: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Cholesky QR: returns (W R^{-1}, R).  Raises NotSPD when W^T W is not SPD."""
+    B = gram(W, W)
+    B = 0.5 * (B + B.T)
+    R = cholesky_upper(B)
+    Q = sla.solve_triangular(R, np.asarray(W, dtype=np.float64).T, trans="T", lower=False).T
+    return Q, R
+
+
+def assemble_pencil(S: list[np.ndarray], HS: list[np.ndarray]) -> tuple[np.ndarray, np.ndarray]:
+    """G = S^T H S and O = S^T S from the lower blocks of eq. Glower.
+
+    ``S`` and ``HS`` are lists of n x k blocks, e.g. [X, W, P] and [HX, HW, HP].
+    Block (a, b) with a > b is S_a^T (H S_b); block (b, a) is its transpose.
+    Diagonal blocks S_a^T H S_a are averaged with their transposes.
+    """
+    m = len(S)
+    ks = [s.shape[1] for s in S]
+    off = np.concatenate([[0], np.cumsum(ks)])
+    N = int(off[-1])
+    G = np.zeros((N, N))
+    O = np.zeros((N, N))
+    for a in range(m):
+        for b in range(a + 1):
+            ga = gram(S[a], HS[b])
+            oa = gram(S[a], S[b])
+            ra, rb = slice(off[a], off[a + 1]), slice(off[b], off[b + 1])
+            if a == b:
+                G[ra, ra] = 0.5 * (ga + ga.T)
+                O[ra, ra] = 0.5 * (oa + oa.T)
+            else:
+                G[ra, rb] = ga
+                G[rb, ra] = ga.T
+                O[ra, rb] = oa
+                O[rb, ra] = oa.T
+    return G, O
+
+
+def rayleigh_ritz(G: np.ndarray, O: np.ndarray, k: int) -> tuple[np.ndarray, np.ndarray]:
+    """Solve G C = O C D (eq. rreig); return the k leftmost (theta, C), ascending.
+
+    O = L L^T;  A = L^{-1} G L^{-T};  A V = V D;  C = L^{-T} V.
+    Raises NotSPD if O is not positive definite.
+    """
+    L = cholesky_upper(O).T
+    Linv_G = sla.solve_triangular(L, G, lower=True)
+    A = sla.solve_triangular(L, Linv_G.T, lower=True).T
+    A = 0.5 * (A + A.T)
+    d, V = np.linalg.eigh(A)
+    C = sla.solve_triangular(L.T, V[:, :k], lower=False)
+    return d[:k].copy(), C

@@ -1,0 +1,121 @@
+"""Pins for the oracle's LOBPCG (Algorithm 1 with the recurrences eqs. upd1-upd2
+and Cholesky QR of Section 3.5): dense LAPACK eigh at n <= 2000, ARPACK at
+n = 20,000, closed-form spectra, and invariants (orthonormal X, Ritz values
+non-increasing, the residual bound |theta - lambda| <= ||r|| / ||x||)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+import synth
+from oracle.lobpcg import ENOCONV, OK, lobpcg
+from synth import workloads as W
+
+
+def dense(A):
+    U = sp.csr_matrix((np.asarray(A.val, dtype=np.float64), A.col, A.row_ptr), shape=(A.n, A.n))
+    return (U + U.T - sp.diags(U.diagonal())).toarray()
+
+
+def solve(A, k=8, nev=5, **kw):
+    H = oracle.SymMatrix.from_csr(A)
+    X0 = W.initial_block(A.n, k, seed=1)
+    return H, lobpcg(H, X0, nev, d=A.diag, **kw)
+
+
+def test_random_sym_1k_vs_dense_eigh():
+    A = W.make_matrix("random_sym_1k")
+    H, r = solve(A)
+    assert r.status == OK
+    lam = np.linalg.eigvalsh(dense(A))[:5]
+    np.testing.assert_allclose(r.theta, lam, rtol=1e-9)
+    # invariants along the way
+    th = np.array(r.theta_hist)
+    gamma = H.gershgorin()
+    assert np.all(np.diff(th, axis=0) <= 1e-12 * gamma)          # Ritz values never increase
+    np.testing.assert_allclose(r.X_all.T @ r.X_all, np.eye(8), atol=1e-10)
+    # residual certificate for each returned pair
+    res = H @ r.X - r.X * r.theta
+    bound = np.linalg.norm(res, axis=0) / np.linalg.norm(r.X, axis=0)
+    assert np.all(np.abs(r.theta - lam) <= bound * (1 + 1e-6) + 1e-12)
+
+
+def test_subspace_matches_eigh():
+    A = synth.random_sym(800, 30, seed=5)
+    Hd = dense(A)
+    H, r = solve(A, tol=1e-9)
+    assert r.status == OK
+    lam, V = np.linalg.eigh(Hd)
+    # principal angles between span(X) and the exact invariant subspace
+    s = np.linalg.svd(V[:, :5].T @ r.X, compute_uv=False)
+    assert s.min() > 1 - 1e-9
+
+
+@pytest.mark.slow
+def test_random_sym_20k_vs_arpack():
+    A = W.make_matrix("random_sym_20k")
+    H, r = solve(A)
+    assert r.status == OK
+    U = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+    Hs = U + U.T - sp.diags(U.diagonal())
+    lam = np.sort(spla.eigsh(Hs, k=6, which="SA", tol=1e-13)[0])[:5]
+    np.testing.assert_allclose(r.theta, lam, rtol=1e-7)
+
+
+def test_diagonal_matrix_one_step():
+    d = np.sort(np.random.default_rng(0).uniform(0, 10, 300))
+    A = synth.diagonal(d)
+    H = oracle.SymMatrix.from_csr(A)
+    # start from a block that is a permutation of unit vectors around the lowest ones
+    X0 = np.zeros((300, 8))
+    X0[np.arange(8), np.arange(8)[::-1]] = 1.0
+    r = lobpcg(H, X0, 5, d=A.diag)
+    assert r.status == OK and r.iters == 0
+    np.testing.assert_allclose(r.theta, d[:5], rtol=1e-15)
+
+
+def test_laplacian_closed_form():
+    n = 120
+    A = synth.laplacian_1d(n)
+    H = oracle.SymMatrix.from_csr(A)
+    r = lobpcg(H, W.initial_block(n, 8, seed=1), 5, tol=1e-10, precond=None, maxiter=3000)
+    assert r.status == OK
+    j = np.arange(1, 6)
+    np.testing.assert_allclose(r.theta, 2 - 2 * np.cos(j * np.pi / (n + 1)), rtol=1e-8)
+
+
+def test_blocks_2x2_closed_form():
+    rng = np.random.default_rng(3)
+    m = 100
+    a, c = rng.uniform(0, 10, m), rng.uniform(0, 10, m)
+    b = rng.uniform(-2, 2, m)
+    A = synth.blocks_2x2(a, b, c)
+    H = oracle.SymMatrix.from_csr(A)
+    r = lobpcg(H, W.initial_block(2 * m, 8, seed=1), 5, tol=1e-10, d=A.diag)
+    assert r.status == OK
+    lo = (a + c) / 2 - np.hypot((a - c) / 2, b)
+    hi = (a + c) / 2 + np.hypot((a - c) / 2, b)
+    lam = np.sort(np.concatenate([lo, hi]))[:5]
+    np.testing.assert_allclose(r.theta, lam, rtol=1e-9, atol=1e-12)
+
+
+def test_maxiter_exhaustion():
+    A = W.make_matrix("random_sym_1k")
+    H, r = solve(A, maxiter=3)
+    assert r.status == ENOCONV and r.iters == 3
+    assert len(r.theta_hist) == 3
+
+
+def test_recurrence_tracks_explicit_product():
+    """H X carried by eqs. upd1-upd2 stays close to the explicit product."""
+    A = synth.random_sym(1000, 30, seed=8)
+    H = oracle.SymMatrix.from_csr(A)
+    seen = {}
+
+    def cb(it, X, R, theta, Wb):
+        seen["X"], seen["R"], seen["theta"] = X.copy(), R.copy(), theta.copy()
+    r = lobpcg(H, W.initial_block(A.n, 8, seed=1), 5, d=A.diag, maxiter=40, callback=cb)
+    X, R, theta = seen["X"], seen["R"], seen["theta"]
+    Rexp = H @ X - X * theta
+    assert np.abs(R - Rexp).max() < 1e-10 * H.gershgorin()
