@@ -1,0 +1,187 @@
+/*
+ * lobpcg.h -- C ABI of the MI355X (gfx950) LOBPCG hot path.
+ *
+ * The library finds the lowest eigenpairs of a large sparse symmetric matrix
+ * H, given by its upper triangle, with the block method of Maris, Yang,
+ * Oryspayev & Cook (arXiv:2109.00485), Algorithm 1: block locally optimal
+ * preconditioned conjugate gradients, one Rayleigh-Ritz step per iteration,
+ * H X and H P carried by the recurrences eqs. upd1-upd2 so that H W is the
+ * only sparse product per iteration.
+ *
+ * Conventions shared by every entry point
+ *  - Blocks of k vectors are n x k, ROW-MAJOR (row i of all k vectors is
+ *    contiguous; paper Section 3.3), device-resident, in the context dtype.
+ *  - Every pointer argument is caller-owned; the library never frees it.
+ *    "device" means memory the HIP runtime can address from gfx950 kernels
+ *    (hipMalloc / torch CUDA tensors); "host" means ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    spmm_sym, precond_apply and gram are asynchronous on that stream;
+ *    create and solve are synchronous with respect to it.
+ *  - Errors are returned as status codes (never thrown across the ABI).
+ *    Scalar and shape checks run on the host before anything is enqueued,
+ *    so they are testable without a GPU.  lobpcg_last_error() returns a
+ *    human-readable message for the last failing call on a context.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LOBPCG_MI355X_H
+#define LOBPCG_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define LOBPCG_OK            0
+#define LOBPCG_EINVAL       -1   /* bad argument or malformed matrix            */
+#define LOBPCG_ENOMEM       -2   /* device allocation failed                    */
+#define LOBPCG_EHIP         -3   /* HIP runtime error                           */
+#define LOBPCG_ENOTSPD      -4   /* Cholesky QR / Rayleigh-Ritz lost definiteness */
+#define LOBPCG_ENOCONV      -5   /* maxiter reached; best iterate still returned */
+#define LOBPCG_ENONFINITE   -6   /* NaN/Inf in matrix values or iterates        */
+#define LOBPCG_EUNSUPPORTED -7   /* valid request the build does not support    */
+
+/* ---- enumerations ---- */
+#define LOBPCG_F32 1             /* FP32 values, blocks and sparse arithmetic   */
+#define LOBPCG_F64 2             /* FP64 everywhere                             */
+
+#define LOBPCG_GRAM_AUTO   0     /* FP64 for F64 contexts, FP32 MFMA for F32    */
+#define LOBPCG_GRAM_F64    1     /* inputs upcast to FP64, FP64 MFMA            */
+#define LOBPCG_GRAM_F32    2     /* FP32 MFMA, FP64 reduction across workgroups */
+#define LOBPCG_GRAM_BF16X3 3     /* split-BF16 (a0b0 + a0b1 + a1b0) MFMA, FP32 inputs */
+
+#define LOBPCG_PRECOND_NONE 0    /* K = I                                       */
+#define LOBPCG_PRECOND_DIAG 1    /* W_ij = R_ij / s(d_i - theta_j)              */
+#define LOBPCG_PRECOND_MLP  2    /* learned scaling from an attached MLP        */
+
+#define LOBPCG_FORMAT_AUTO  0    /* tiled when tiles are dense enough, else CSR */
+#define LOBPCG_FORMAT_CSR   1    /* row-split CSR of the strict upper triangle  */
+#define LOBPCG_FORMAT_TILED 2    /* tile-row ordered sparse tiles               */
+
+typedef struct lobpcg_ctx lobpcg_ctx;
+typedef struct lobpcg_mlp lobpcg_mlp;
+
+typedef struct {
+    int dtype;        /* LOBPCG_F32 (default) or LOBPCG_F64                          */
+    int gram;         /* LOBPCG_GRAM_*                                               */
+    int format;       /* LOBPCG_FORMAT_*                                             */
+    int tile;         /* tile edge of the tiled format; 64 is the only value built   */
+    int kmax;         /* largest block size this context will be used with (<= 16)   */
+    double tau_rel;   /* convergence floor tau = tau_rel * gamma (default 1e-3)      */
+    double eps_rel;   /* preconditioner guard eps = eps_rel * gamma (default 1e-5)   */
+} lobpcg_opts;
+
+typedef struct {
+    int iters;            /* LOBPCG iterations performed                        */
+    int n_spmm;           /* sparse products performed (incl. confirmations)    */
+    int p_dropped;        /* iterations whose Rayleigh-Ritz dropped P           */
+    int cholqr_retries;   /* Cholesky QR retries after re-projection            */
+    int confirmations;    /* explicit H X recomputations on apparent convergence */
+    int status;           /* same value the call returned                       */
+    double gamma;         /* Gershgorin bound max_i sum_j |H_ij|                 */
+    /* optional, caller-owned host arrays of maxiter*k doubles (NULL to skip):
+       Ritz values and relative residual norms after every iteration          */
+    double *theta_hist;
+    double *rel_hist;
+    /* optional per-phase device time in seconds (filled when timing != 0)      */
+    int timing;
+    double t_spmm, t_precond_update, t_gram, t_rr, t_orth, t_total;
+} lobpcg_info;
+
+/* Fill *o with the defaults: F32, GRAM_AUTO, FORMAT_AUTO, tile 64, kmax 16,
+ * tau_rel 1e-3, eps_rel 1e-5. */
+void lobpcg_opts_default(lobpcg_opts *o);
+
+/*
+ * lobpcg_create -- validate H, build the library's own device copy of it, and
+ * allocate every workspace once (the paper creates its solver handles and
+ * workspaces outside the iteration loop, Section 4.4).
+ *
+ *   n        matrix dimension, 1 <= n < 2^31
+ *   row_ptr  device, int64[n+1], CSR row offsets of the UPPER triangle of H,
+ *            diagonal included (the paper stores half of the symmetric H,
+ *            Section 3.1)
+ *   col      device, int32[nnz], nnz = row_ptr[n]; within each row strictly
+ *            ascending, col >= row, and the first entry of row i is (i, i)
+ *   val      device, nnz values in opts->dtype
+ *   opts     host, may be NULL for defaults
+ * The caller may free its arrays once create returns.  Malformed CSR content
+ * is detected by a device validation pass and returns LOBPCG_EINVAL;
+ * non-finite values return LOBPCG_ENONFINITE.  *out is NULL on failure.
+ */
+int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                  const void *val, const lobpcg_opts *opts, void *stream);
+
+void lobpcg_destroy(lobpcg_ctx *ctx);
+
+/*
+ * lobpcg_spmm_sym -- Y = H X from the stored upper triangle: each stored
+ * off-diagonal h_ij (i < j) contributes h_ij X_j to Y_i and h_ij X_i to Y_j
+ * (Algorithm 2, applied to the stored part and its transpose, Section 3.2).
+ *   X  device, n x k row-major, read-only
+ *   Y  device, n x k row-major, overwritten; must not alias X
+ *   1 <= k <= kmax
+ */
+int lobpcg_spmm_sym(lobpcg_ctx *ctx, const void *X, void *Y, int k, void *stream);
+
+/*
+ * lobpcg_precond_apply -- W = K^{-1} R, Algorithm 1 line 6.  With
+ * LOBPCG_PRECOND_DIAG, K is the diagonal of H shifted per column by the Ritz
+ * value theta_j (the 1x1-tile case of the block-diagonal preconditioner of
+ * Section 3.4): W_ij = R_ij / s(d_i - theta_j), s(x) = x if |x| >= eps else
+ * +-eps (sign of x, + for 0), eps = eps_rel * gamma.  With LOBPCG_PRECOND_MLP
+ * the attached network supplies the scaling (lobpcg_set_mlp).
+ *   R      device, n x k row-major
+ *   theta  device, double[k]
+ *   W      device, n x k row-major, written (may alias R)
+ */
+int lobpcg_precond_apply(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k,
+                         int kind, void *stream);
+
+/*
+ * lobpcg_gram -- G = A^T B for tall-skinny blocks (the products that form the
+ * projected matrices of eqs. go / Glower and the Cholesky QR Gram W^T W,
+ * Section 3.5), reduced across the whole column in FP64.
+ *   A  device, n x ka row-major;  B device, n x kb row-major (may alias A)
+ *   G  device, double[ka*kb], row-major ka x kb, overwritten
+ *   1 <= ka, kb <= 48; prec is a LOBPCG_GRAM_* value (BF16X3 needs an F32 context)
+ */
+int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B, int kb, double *G,
+                int prec, void *stream);
+
+/*
+ * lobpcg_solve -- lowest nev eigenpairs by Algorithm 1.
+ *   k        block size, nev <= k <= kmax, 3k <= n
+ *   X        device, n x k row-major: the starting block X0 on entry, the Ritz
+ *            vectors (ascending Ritz values) on return
+ *   evals    host, double[k]: Ritz values, ascending
+ *   rel      host, double[k] or NULL: relative residual norms
+ *            ||r_j|| / (max(|theta_j|, tau) ||x_j||)
+ *   tol      > 0, convergence threshold on rel_j for j < nev
+ *   maxiter  >= 0
+ *   precond  LOBPCG_PRECOND_*
+ *   info     host, may be NULL
+ * The run ends when the nev wanted columns meet tol and an explicit product
+ * H X confirms it (the recurrences eqs. upd1-upd2 drift in finite precision).
+ * Returns LOBPCG_ENOCONV when maxiter is reached (X and evals still written).
+ */
+int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *X, double *evals, double *rel, double tol,
+                 int maxiter, int precond, lobpcg_info *info, void *stream);
+
+/* Matrix facts computed at create: n, stored nnz (incl. diagonal), format in
+ * use, dtype, and the Gershgorin bound gamma.  Any output pointer may be NULL. */
+int lobpcg_query(const lobpcg_ctx *ctx, int64_t *n, int64_t *nnz, int *format, int *dtype,
+                 double *gamma);
+
+/* Device copy of the diagonal d (n values, context dtype) into `d`. */
+int lobpcg_get_diag(lobpcg_ctx *ctx, void *d, void *stream);
+
+const char *lobpcg_strerror(int status);
+const char *lobpcg_last_error(const lobpcg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOBPCG_MI355X_H */

@@ -1,0 +1,240 @@
+// Tall-skinny Gram products G = A^T B on the matrix cores.
+//
+// The projected matrices of the Rayleigh-Ritz step (eqs. go, Glower) and the
+// Cholesky QR Gram W^T W (Section 3.5) are products of n x k blocks.  The
+// row dimension n is the MFMA reduction (K) dimension: each wavefront walks a
+// strided set of 16-row slabs and accumulates 16x16 output tiles in MFMA
+// accumulators; the four wavefronts of a workgroup are summed in LDS and each
+// workgroup writes one FP64 partial, which a second kernel sums in a fixed
+// order (deterministic).
+//
+// Precisions: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32), and
+// split-BF16 "x3" for FP32 inputs: a = a0 + a1 with a0 = bf16(a),
+// a1 = bf16(a - a0), and a.b ~ a0.b0 + a0.b1 + a1.b0 (v_mfma_f32_16x16x16bf16_1k).
+//
+// MFMA operand layout used (16x16xK, wave64): lane l supplies
+// A[i = l % 16][kk] and B[kk][j = l % 16] for the kk owned by lane group l / 16;
+// the four outputs of lane l are D[4 * (l / 16) + r][l % 16], r = 0..3.
+#include "internal.hpp"
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GRAM_THREADS = 256;
+constexpr int GRAM_WAVES = GRAM_THREADS / LOBPCG_WAVE;
+
+__device__ inline unsigned short bf16_rne(float x) {
+    unsigned int u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+enum Mode { M_F64 = 0, M_F32 = 1, M_BF16X3 = 2 };
+
+struct GramDev {
+    const void *a[3];
+    const void *b[6];
+    int na, nb, wa, wb;
+    int64_t n;
+};
+
+// per-lane column pointer for a 16-wide tile of a concatenated block list
+template <typename TI>
+__device__ inline const TI *col_ptr(const void *const *blocks, int nblocks, int w, int m) {
+    if (m >= nblocks * w) return nullptr;
+    return (const TI *)blocks[m / w] + (m % w);
+}
+
+template <typename TI, int MODE, int MT, int NT>
+__global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, double *__restrict__ partial) {
+    using Acc = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
+    using AccS = typename std::conditional<MODE == M_F64, double, float>::type;
+    const int lane = threadIdx.x % LOBPCG_WAVE;
+    const int wave = threadIdx.x / LOBPCG_WAVE;
+    const int li = lane % 16, lg = lane / 16;
+    const int KA = g.na * g.wa, KB = g.nb * g.wb;
+
+    const TI *pa[MT];
+    const TI *pb[NT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) pa[t] = col_ptr<TI>(g.a, g.na, g.wa, 16 * t + li);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) pb[t] = col_ptr<TI>(g.b, g.nb, g.wb, 16 * t + li);
+
+    Acc acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+    const int64_t nslab = (g.n + 15) / 16;
+    const int64_t wave_id = (int64_t)blockIdx.x * GRAM_WAVES + wave;
+    const int64_t nwaves = (int64_t)gridDim.x * GRAM_WAVES;
+    for (int64_t slab = wave_id; slab < nslab; slab += nwaves) {
+        const int64_t r0 = slab * 16;
+        if constexpr (MODE == M_BF16X3) {
+            // K = 16 rows per instruction; lane group lg owns rows r0 + 4*lg + t
+            s16x4 a0[MT], a1[MT], b0[NT], b1[NT];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    int64_t r = r0 + 4 * lg + t;
+                    float v = (pa[i] && r < g.n) ? (float)pa[i][r * g.wa] : 0.0f;
+                    unsigned short h = bf16_rne(v);
+                    a0[i][t] = (short)h;
+                    a1[i][t] = (short)bf16_rne(v - bf16_to_f32(h));
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    int64_t r = r0 + 4 * lg + t;
+                    float v = (pb[j] && r < g.n) ? (float)pb[j][r * g.wb] : 0.0f;
+                    unsigned short h = bf16_rne(v);
+                    b0[j][t] = (short)h;
+                    b1[j][t] = (short)bf16_rne(v - bf16_to_f32(h));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[i], b0[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[i], b1[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[i], b0[j], acc[i][j], 0, 0, 0);
+                }
+        } else {
+            // K = 4 rows per instruction, four instructions per 16-row slab
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t r = r0 + 4 * t + lg;
+                AccS av[MT], bv[NT];
+#pragma unroll
+                for (int i = 0; i < MT; ++i) av[i] = (pa[i] && r < g.n) ? (AccS)pa[i][r * g.wa] : AccS(0);
+#pragma unroll
+                for (int j = 0; j < NT; ++j) bv[j] = (pb[j] && r < g.n) ? (AccS)pb[j][r * g.wb] : AccS(0);
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        if constexpr (MODE == M_F64)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+                        else
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+        }
+    }
+
+    // sum the wavefronts of this workgroup in LDS (FP64), one wave at a time
+    __shared__ double red[MT * NT * 4 * LOBPCG_WAVE];
+    for (int w = 0; w < GRAM_WAVES; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        int idx = ((i * NT + j) * 4 + r) * LOBPCG_WAVE + lane;
+                        double v = (double)acc[i][j][r];
+                        red[idx] = (w == 0) ? v : red[idx] + v;
+                    }
+        }
+        __syncthreads();
+    }
+    double *out = partial + (size_t)blockIdx.x * KA * KB;
+    for (int e = threadIdx.x; e < MT * NT * 4 * LOBPCG_WAVE; e += GRAM_THREADS) {
+        int l = e % LOBPCG_WAVE, r = (e / LOBPCG_WAVE) % 4, tile = e / (4 * LOBPCG_WAVE);
+        int i = tile / NT, j = tile % NT;
+        int m = 16 * i + 4 * (l / 16) + r, nn = 16 * j + (l % 16);
+        if (m < KA && nn < KB) out[m * KB + nn] = red[e];
+    }
+}
+
+__global__ void gram_reduce_kernel(const double *__restrict__ partial, int nparts, int count,
+                                   double *__restrict__ out) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * count + e];
+    out[e] = s;
+}
+
+template <typename TI, int MODE>
+int dispatch_tiles(int MT, int NT, int grid, const GramDev &g, double *partial, hipStream_t s) {
+#define GRAM_CASE(a, b)                                                                        \
+    if (MT == a && NT == b) {                                                                  \
+        gram_partial_kernel<TI, MODE, a, b><<<grid, GRAM_THREADS, 0, s>>>(g, partial);         \
+        return LOBPCG_OK;                                                                      \
+    }
+    GRAM_CASE(1, 1) GRAM_CASE(1, 2) GRAM_CASE(1, 3) GRAM_CASE(1, 4) GRAM_CASE(1, 5) GRAM_CASE(1, 6)
+    GRAM_CASE(2, 1) GRAM_CASE(2, 2) GRAM_CASE(2, 3) GRAM_CASE(2, 4) GRAM_CASE(2, 5) GRAM_CASE(2, 6)
+    GRAM_CASE(3, 1) GRAM_CASE(3, 2) GRAM_CASE(3, 3) GRAM_CASE(3, 4) GRAM_CASE(3, 5) GRAM_CASE(3, 6)
+#undef GRAM_CASE
+    return LOBPCG_EUNSUPPORTED;
+}
+
+}  // namespace
+
+int launch_gram(lobpcg_ctx *ctx, const GramArgs &ga, int prec, double *out, hipStream_t s) {
+    const int KA = ga.na * ga.wa, KB = ga.nb * ga.wb;
+    if (KA < 1 || KB < 1 || KA > 48 || KB > 96) return set_err(ctx, LOBPCG_EINVAL, "gram: %dx%d too large", KA, KB);
+    const int MT = (KA + 15) / 16, NT = (KB + 15) / 16;
+    GramDev g;
+    for (int i = 0; i < 3; ++i) g.a[i] = i < ga.na ? ga.a[i] : nullptr;
+    for (int i = 0; i < 6; ++i) g.b[i] = i < ga.nb ? ga.b[i] : nullptr;
+    g.na = ga.na; g.nb = ga.nb; g.wa = ga.wa; g.wb = ga.wb; g.n = ctx->n;
+    const int64_t nslab = (ctx->n + 15) / 16;
+    // enough slabs per wavefront to amortise the partial write, at most one partial per slot
+    int grid = (int)std::min<int64_t>(ctx->gram_max_wg, std::max<int64_t>(1, (nslab + 4 * GRAM_WAVES - 1) / (4 * GRAM_WAVES)));
+    grid = std::min(grid, 256);
+    int rc;
+    if (prec == LOBPCG_GRAM_AUTO) prec = ctx->gram;
+    if (ctx->dtype == LOBPCG_F64) {
+        if (prec != LOBPCG_GRAM_F64) return set_err(ctx, LOBPCG_EINVAL, "gram: FP64 context needs GRAM_F64");
+        rc = dispatch_tiles<double, M_F64>(MT, NT, grid, g, ctx->gram_partial, s);
+    } else if (prec == LOBPCG_GRAM_F64) {
+        rc = dispatch_tiles<float, M_F64>(MT, NT, grid, g, ctx->gram_partial, s);
+    } else if (prec == LOBPCG_GRAM_F32) {
+        rc = dispatch_tiles<float, M_F32>(MT, NT, grid, g, ctx->gram_partial, s);
+    } else if (prec == LOBPCG_GRAM_BF16X3) {
+        rc = dispatch_tiles<float, M_BF16X3>(MT, NT, grid, g, ctx->gram_partial, s);
+    } else {
+        return set_err(ctx, LOBPCG_EINVAL, "gram: bad precision %d", prec);
+    }
+    if (rc != LOBPCG_OK) return set_err(ctx, rc, "gram: no kernel for %dx%d tiles", MT, NT);
+    gram_reduce_kernel<<<ceil_div(KA * KB, 256), 256, 0, s>>>(ctx->gram_partial, grid, KA * KB, out);
+    return LOBPCG_OK;
+}
+
+extern "C" int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B, int kb, double *G, int prec,
+                           void *stream) {
+    if (!ctx) return LOBPCG_EINVAL;
+    if (!A || !B || !G) return set_err(ctx, LOBPCG_EINVAL, "gram: null pointer");
+    if (ka < 1 || kb < 1 || ka > 48 || kb > 48) return set_err(ctx, LOBPCG_EINVAL, "gram: ka, kb must be in [1,48]");
+    if (prec < LOBPCG_GRAM_AUTO || prec > LOBPCG_GRAM_BF16X3) return set_err(ctx, LOBPCG_EINVAL, "gram: bad precision");
+    if (prec == LOBPCG_GRAM_BF16X3 && ctx->dtype != LOBPCG_F32)
+        return set_err(ctx, LOBPCG_EINVAL, "gram: BF16X3 needs an FP32 context");
+    if (ctx->dtype == LOBPCG_F64 && (prec == LOBPCG_GRAM_F32))
+        return set_err(ctx, LOBPCG_EINVAL, "gram: FP32 Gram of FP64 blocks is not offered");
+    GramArgs ga{};
+    ga.a[0] = A;
+    ga.b[0] = B;
+    ga.na = 1;
+    ga.nb = 1;
+    ga.wa = ka;
+    ga.wb = kb;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = launch_gram(ctx, ga, prec, G, s);
+    if (rc != LOBPCG_OK) return rc;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(ctx, LOBPCG_EHIP, "gram launch: %s", hipGetErrorString(e));
+    return LOBPCG_OK;
+}

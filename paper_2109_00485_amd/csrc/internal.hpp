@@ -1,0 +1,120 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "lobpcg.h"
+
+#define LOBPCG_WAVE 64
+
+// Device-side error flags raised by validation and by the dense kernels.
+enum : int {
+    FLAG_BAD_ROWPTR = 1,
+    FLAG_BAD_COL = 2,
+    FLAG_NO_DIAG = 4,
+    FLAG_UNSORTED = 8,
+    FLAG_NONFINITE = 16,
+    FLAG_CHOLQR_FAIL = 32,   // Cholesky of W^T W failed; later kernels of the iteration skip
+    FLAG_RR_FAIL = 64,       // Rayleigh-Ritz failed even without P
+    FLAG_RR_PDROP = 128,     // Rayleigh-Ritz dropped P this iteration
+};
+
+// Per-iteration report copied to the host (doubles, padded to kmax).
+struct Report {
+    double theta[16];
+    double rnorm2[16];
+    double xnorm2[16];
+    double flags;     // device flags as a double (exact for small ints)
+    double nblk_used; // blocks used by the last Rayleigh-Ritz
+    double pad[6];
+};
+
+// Tiled format descriptor (tile-row ordered; see spmm.hip).
+struct TiledFormat {
+    int64_t ntiles = 0;        // stored off-diagonal-or-diagonal tiles
+    int64_t ntilerows = 0;
+    int64_t *tile_nnz_off = nullptr;   // ntiles+1 offsets into the entry arrays
+    int32_t *tile_col = nullptr;       // tile column index J per tile
+    int32_t *tile_row = nullptr;       // tile row index I per tile
+    uint16_t *ent_rc = nullptr;        // packed (r | c << 8) local coordinates
+    void *ent_val = nullptr;           // values (context dtype)
+    int64_t nent = 0;
+    int32_t *work_tile0 = nullptr;     // per work item: first tile
+    int64_t nwork = 0;
+};
+
+struct lobpcg_ctx {
+    int64_t n = 0, nnz = 0, nnz_off = 0;
+    int dtype = LOBPCG_F32, format = LOBPCG_FORMAT_CSR, tile = 64, kmax = 16, gram = LOBPCG_GRAM_AUTO;
+    size_t esz = 4;
+    double tau_rel = 1e-3, eps_rel = 1e-5, gamma = 0.0;
+    int device = 0;
+    // strict upper triangle in CSR + diagonal
+    int64_t *rp = nullptr;
+    int32_t *ci = nullptr;
+    void *val = nullptr;
+    void *diag = nullptr;
+    TiledFormat tiled;
+    // MLP features (float): full-row off-diagonal 1-norm and 64-row tile mean |h|
+    float *feat_rownorm = nullptr, *feat_tilemean = nullptr;
+    // LOBPCG blocks (n x kmax each)
+    void *X = nullptr, *W = nullptr, *P = nullptr, *HX = nullptr, *HW = nullptr, *HP = nullptr;
+    // Gram scratch
+    double *gram_partial = nullptr;  // [gram_max_wg][48*96]
+    int gram_max_wg = 0;
+    double *gram_out = nullptr;      // up to 48 x 96
+    double *gram_out2 = nullptr;     // a second k x k result (Cholesky QR)
+    // small dense FP64 state
+    double *rr_C = nullptr;          // 48 x 16
+    double *rr_theta = nullptr;      // 16
+    double *orth_rinv = nullptr;     // 16 x 16
+    double *norm_partial = nullptr;  // [norm_max_wg][3*16]
+    int norm_max_wg = 0;
+    Report *report_dev = nullptr;
+    Report *report_host = nullptr;   // pinned
+    int *dflags = nullptr;
+    lobpcg_mlp *mlp = nullptr;
+    hipEvent_t ev[8] = {};
+    std::string err;
+};
+
+// error helpers -------------------------------------------------------------
+int set_err(lobpcg_ctx *ctx, int code, const char *fmt, ...);
+
+#define HIP_TRY(ctx, expr)                                                               \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return set_err((ctx), LOBPCG_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// launchers implemented across the .hip files --------------------------------
+int launch_spmm(lobpcg_ctx *ctx, const void *X, void *Y, int k, hipStream_t s);
+int launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// Gram: G = A^T B with A = [a_0 .. a_{na-1}] (each n x wa), B = [b_0 ..] (each n x wb).
+struct GramArgs {
+    const void *a[3];
+    const void *b[6];
+    int na, nb, wa, wb;
+};
+int launch_gram(lobpcg_ctx *ctx, const GramArgs &g, int prec, double *out, hipStream_t s);
+
+// out = sum_b in_b * M_b  (M_b k x k FP64 row-major; NULL = identity; coef_b scales)
+int launch_combine(lobpcg_ctx *ctx, int k, int nin, const void *const *in, const double *const *mats,
+                   const double *coef, void *out, hipStream_t s);
+
+int launch_cholinv(lobpcg_ctx *ctx, int k, const double *B, double *rinv, hipStream_t s);
+int launch_rr(lobpcg_ctx *ctx, int k, int nblk, hipStream_t s);
+int launch_update(lobpcg_ctx *ctx, int k, int nblk, int precond, int write_w, hipStream_t s);
+int launch_residual(lobpcg_ctx *ctx, int k, int precond, const double *theta, int write_w, hipStream_t s);
+int launch_rayleigh_quotients(lobpcg_ctx *ctx, int k, hipStream_t s);
+int launch_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, int kind,
+                   hipStream_t s);
+int mlp_precond_ready(lobpcg_ctx *ctx);

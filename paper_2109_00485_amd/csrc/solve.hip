@@ -1,0 +1,244 @@
+// The LOBPCG driver (Algorithm 1).  Every step runs on the device; the host
+// only reads a small per-iteration report (Ritz values, residual and column
+// norms, flags: about 3k doubles) to take the convergence decision.
+//
+// One iteration:
+//   W <- W - X (X^T W); Cholesky QR of W           (Section 3.5)
+//   HW = H W                                        (the only sparse product)
+//   G, O from the lower blocks of [X W P]^T [X W P HX HW HP]   (eq. Glower)
+//   Rayleigh-Ritz on (G, O) -> C, Theta             (eq. rreig)
+//   X, HX, P, HP <- [X W P] C, [HX HW HP] C, ...    (eqs. xupd, pupd, upd1-upd2)
+//   R = HX - X Theta, column norms, W = K^{-1} R    (lines 10 and 6)
+// Convergence: rel_j = ||r_j|| / (max(|theta_j|, tau) ||x_j||) <= tol for the
+// nev wanted columns; then H X is recomputed explicitly, theta_j becomes the
+// Rayleigh quotient x_j^T H x_j / x_j^T x_j, and the test is repeated.
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s);
+int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s);
+
+namespace {
+
+struct Timer {
+    lobpcg_ctx *ctx;
+    hipStream_t s;
+    bool on;
+    void mark(int i) {
+        if (on) (void)hipEventRecord(ctx->ev[i], s);
+    }
+    double span(int a, int b) {
+        if (!on) return 0.0;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]);
+        return ms * 1e-3;
+    }
+};
+
+int read_report(lobpcg_ctx *ctx, hipStream_t s) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->report_host, ctx->report_dev, sizeof(Report), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return LOBPCG_OK;
+}
+
+void rel_from_report(const lobpcg_ctx *ctx, int k, double tau, double *rel, bool *finite) {
+    const Report &r = *ctx->report_host;
+    *finite = true;
+    for (int j = 0; j < k; ++j) {
+        double rn = std::sqrt(r.rnorm2[j]), xn = std::sqrt(r.xnorm2[j]);
+        rel[j] = rn / (std::max(std::fabs(r.theta[j]), tau) * xn);
+        if (!std::isfinite(rel[j]) || !std::isfinite(r.theta[j])) *finite = false;
+    }
+}
+
+}  // namespace
+
+extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double *evals, double *rel_out, double tol,
+                            int maxiter, int precond, lobpcg_info *info, void *stream) {
+    if (!ctx) return LOBPCG_EINVAL;
+    if (!Xuser || !evals) return set_err(ctx, LOBPCG_EINVAL, "solve: null pointer");
+    if (k < 1 || k > ctx->kmax) return set_err(ctx, LOBPCG_EINVAL, "solve: k=%d outside [1,%d]", k, ctx->kmax);
+    if (nev < 1 || nev > k) return set_err(ctx, LOBPCG_EINVAL, "solve: need 1 <= nev <= k");
+    if ((int64_t)3 * k > ctx->n) return set_err(ctx, LOBPCG_EINVAL, "solve: need 3k <= n");
+    if (!(tol > 0)) return set_err(ctx, LOBPCG_EINVAL, "solve: tol must be > 0");
+    if (maxiter < 0) return set_err(ctx, LOBPCG_EINVAL, "solve: maxiter must be >= 0");
+    if (precond != LOBPCG_PRECOND_NONE && precond != LOBPCG_PRECOND_DIAG && precond != LOBPCG_PRECOND_MLP)
+        return set_err(ctx, LOBPCG_EINVAL, "solve: bad preconditioner %d", precond);
+    if (precond == LOBPCG_PRECOND_MLP) {
+        int rc = mlp_precond_ready(ctx);
+        if (rc != LOBPCG_OK) return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t blk = (size_t)ctx->n * k * ctx->esz;
+    const double tau = ctx->tau_rel * ctx->gamma;
+    const bool timing = info && info->timing;
+    Timer tm{ctx, s, timing};
+    double t_spmm = 0, t_upd = 0, t_gram = 0, t_rr = 0, t_orth = 0;
+    int n_spmm = 0, p_dropped = 0, retries = 0, confirmations = 0;
+    const int upd_precond = precond == LOBPCG_PRECOND_MLP ? LOBPCG_PRECOND_NONE : precond;
+    auto apply_mlp = [&]() -> int {
+        if (precond == LOBPCG_PRECOND_MLP) return launch_mlp_precond(ctx, ctx->W, ctx->rr_theta, ctx->W, k, s);
+        return LOBPCG_OK;
+    };
+    auto gram_rr_input = [&](int nb) -> int {
+        GramArgs g{};
+        void *S[3] = {ctx->X, ctx->W, ctx->P};
+        void *HS[3] = {ctx->HX, ctx->HW, ctx->HP};
+        g.na = nb;
+        g.nb = 2 * nb;
+        g.wa = g.wb = k;
+        for (int b = 0; b < nb; ++b) {
+            g.a[b] = S[b];
+            g.b[b] = S[b];
+            g.b[nb + b] = HS[b];
+        }
+        return launch_gram(ctx, g, ctx->gram, ctx->gram_out, s);
+    };
+    int rc;
+#define TRY(expr)                             \
+    do {                                      \
+        rc = (expr);                          \
+        if (rc != LOBPCG_OK) return rc;       \
+    } while (0)
+
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->X, Xuser, blk, hipMemcpyDeviceToDevice, s));
+    TRY(launch_set_flags(ctx, 0, 0, s));
+    tm.mark(0);
+    // Algorithm 1, lines 1-4: Rayleigh-Ritz on X0
+    TRY(launch_spmm(ctx, ctx->X, ctx->HX, k, s));
+    ++n_spmm;
+    tm.mark(1);
+    TRY(gram_rr_input(1));
+    tm.mark(2);
+    TRY(launch_rr(ctx, k, 1, s));
+    tm.mark(3);
+    TRY(launch_update(ctx, k, 1, upd_precond, 1, s));
+    TRY(apply_mlp());
+    tm.mark(4);
+    TRY(read_report(ctx, s));
+    t_spmm += tm.span(0, 1); t_gram += tm.span(1, 2); t_rr += tm.span(2, 3); t_upd += tm.span(3, 4);
+    if ((int)ctx->report_host->flags & FLAG_RR_FAIL) return set_err(ctx, LOBPCG_ENOTSPD, "initial Rayleigh-Ritz failed");
+
+    std::vector<double> rel(k);
+    bool finite = true;
+    bool have_p = false;
+    int it = 0;
+    int status = LOBPCG_ENOCONV;
+    for (;;) {
+        rel_from_report(ctx, k, tau, rel.data(), &finite);
+        if (!finite) { status = set_err(ctx, LOBPCG_ENONFINITE, "non-finite residual at iteration %d", it); break; }
+        bool conv = true;
+        for (int j = 0; j < nev; ++j) conv = conv && rel[j] <= tol;
+        if (conv) {
+            // confirm with an explicit product (the recurrences drift)
+            ++confirmations;
+            tm.mark(0);
+            TRY(launch_spmm(ctx, ctx->X, ctx->HX, k, s));
+            ++n_spmm;
+            tm.mark(1);
+            GramArgs g{};
+            g.a[0] = ctx->X;
+            g.b[0] = ctx->X;
+            g.b[1] = ctx->HX;
+            g.na = 1; g.nb = 2; g.wa = g.wb = k;
+            TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out, s));
+            TRY(launch_rayleigh_quotients(ctx, k, s));
+            tm.mark(2);
+            TRY(launch_update(ctx, k, 0, upd_precond, 1, s));
+            TRY(apply_mlp());
+            tm.mark(3);
+            TRY(read_report(ctx, s));
+            t_spmm += tm.span(0, 1); t_gram += tm.span(1, 2); t_upd += tm.span(2, 3);
+            rel_from_report(ctx, k, tau, rel.data(), &finite);
+            if (!finite) { status = set_err(ctx, LOBPCG_ENONFINITE, "non-finite residual at iteration %d", it); break; }
+            conv = true;
+            for (int j = 0; j < nev; ++j) conv = conv && rel[j] <= tol;
+            if (conv) { status = LOBPCG_OK; break; }
+        }
+        if (it >= maxiter) break;
+        ++it;
+        bool done_iter = false;
+        for (int attempt = 0; attempt < 2 && !done_iter; ++attempt) {
+            TRY(launch_set_flags(ctx, 0, 0, s));
+            tm.mark(0);
+            // W <- W - X (X^T W), then Cholesky QR
+            {
+                GramArgs g{};
+                g.a[0] = ctx->X; g.b[0] = ctx->W; g.na = g.nb = 1; g.wa = g.wb = k;
+                TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
+                const void *in[2] = {ctx->W, ctx->X};
+                const double *mats[2] = {nullptr, ctx->gram_out2};
+                const double coef[2] = {1.0, -1.0};
+                TRY(launch_combine(ctx, k, 2, in, mats, coef, ctx->W, s));
+                g.a[0] = ctx->W;
+                TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
+                TRY(launch_cholinv(ctx, k, ctx->gram_out2, ctx->orth_rinv, s));
+                const void *in1[1] = {ctx->W};
+                const double *mats1[1] = {ctx->orth_rinv};
+                const double coef1[1] = {1.0};
+                TRY(launch_combine(ctx, k, 1, in1, mats1, coef1, ctx->W, s));
+            }
+            tm.mark(1);
+            TRY(launch_spmm(ctx, ctx->W, ctx->HW, k, s));
+            tm.mark(2);
+            const int nb = have_p ? 3 : 2;
+            TRY(gram_rr_input(nb));
+            tm.mark(3);
+            TRY(launch_rr(ctx, k, nb, s));
+            tm.mark(4);
+            TRY(launch_update(ctx, k, nb, upd_precond, 1, s));
+            TRY(apply_mlp());
+            tm.mark(5);
+            TRY(read_report(ctx, s));
+            const int fl = (int)ctx->report_host->flags;
+            if (fl & FLAG_CHOLQR_FAIL) {
+                ++retries;
+                continue;  // W was only projected; project again and retry once
+            }
+            ++n_spmm;
+            t_orth += tm.span(0, 1); t_spmm += tm.span(1, 2); t_gram += tm.span(2, 3);
+            t_rr += tm.span(3, 4); t_upd += tm.span(4, 5);
+            if (fl & FLAG_RR_FAIL) {
+                return set_err(ctx, LOBPCG_ENOTSPD, "Rayleigh-Ritz failed at iteration %d", it);
+            }
+            if (fl & FLAG_RR_PDROP) ++p_dropped;
+            have_p = true;
+            done_iter = true;
+        }
+        if (!done_iter) { status = set_err(ctx, LOBPCG_ENOTSPD, "Cholesky QR failed twice at iteration %d", it); break; }
+        if (info && info->theta_hist && info->rel_hist) {
+            rel_from_report(ctx, k, tau, rel.data(), &finite);
+            for (int j = 0; j < k; ++j) {
+                info->theta_hist[(size_t)(it - 1) * k + j] = ctx->report_host->theta[j];
+                info->rel_hist[(size_t)(it - 1) * k + j] = rel[j];
+            }
+        }
+    }
+#undef TRY
+    HIP_TRY(ctx, hipMemcpyAsync(Xuser, ctx->X, blk, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    rel_from_report(ctx, k, tau, rel.data(), &finite);
+    for (int j = 0; j < k; ++j) {
+        evals[j] = ctx->report_host->theta[j];
+        if (rel_out) rel_out[j] = rel[j];
+    }
+    if (info) {
+        info->iters = it;
+        info->n_spmm = n_spmm;
+        info->p_dropped = p_dropped;
+        info->cholqr_retries = retries;
+        info->confirmations = confirmations;
+        info->status = status;
+        info->gamma = ctx->gamma;
+        info->t_spmm = t_spmm;
+        info->t_precond_update = t_upd;
+        info->t_gram = t_gram;
+        info->t_rr = t_rr;
+        info->t_orth = t_orth;
+        info->t_total = t_spmm + t_upd + t_gram + t_rr + t_orth;
+    }
+    if (status == LOBPCG_ENOCONV) set_err(ctx, status, "not converged after %d iterations", it);
+    return status;
+}

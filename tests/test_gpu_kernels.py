@@ -1,0 +1,182 @@
+"""GPU parity of the individual hot-path kernels against the FP64 oracle,
+called through the C ABI (ctypes binding).
+
+Bars: bitwise for integer-valued inputs (any summation order is exact there,
+so a race or a lost atomic update shows up as a mismatch); FP32 SpMM within
+1e-5 of the condition-aware row scale ||(|H||X|)_i||; FP64 within 1e-12 of it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import row_error, torch_cuda, to_dev, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def int_matrix(n, draws, seed, vmax=4):
+    """random_sym pattern with small integer values (exact in FP32 and BF16)."""
+    A = synth.random_sym(n, draws, seed=seed, f32=False)
+    rng = np.random.default_rng(seed)
+    v = rng.integers(-vmax, vmax + 1, size=A.nnz).astype(np.float64)
+    v[v == 0] = 1.0
+    diag_pos = A.row_ptr[:-1]
+    v[diag_pos] = rng.integers(0, 9, size=A.n)
+    return synth.ArrayCSR(A.n, A.row_ptr.copy(), A.col.copy(), v)
+
+
+MATRICES = {
+    "random_sym": lambda: synth.random_sym(3000, 20, seed=3),
+    "tiled": lambda: synth.tiled(64 * 40, tile=64, tile_draws=5, p=0.1, seed=2),
+    "zipf": lambda: synth.zipf(4000, lmin=4, lmax=400, seed=5),
+    "tiny": lambda: synth.random_sym(7, 3, seed=1),
+}
+
+
+@pytest.mark.parametrize("name", list(MATRICES))
+@pytest.mark.parametrize("k", [1, 5, 8, 16])
+@pytest.mark.parametrize("f32", [True, False])
+def test_spmm_parity(name, k, f32):
+    torch = torch_cuda()
+    A = MATRICES[name]()
+    dt = np.float32 if f32 else np.float64
+    ctx = upload(A, f32)
+    X = synth.gaussian_block(A.n, k, seed=17).astype(dt)
+    Y = ctx.spmm_sym(to_dev(X, dt)).cpu().numpy()
+    H = oracle.SymMatrix(A.n, A.row_ptr, A.col, np.asarray(A.val, dtype=dt))
+    Yref = H @ X.astype(np.float64)
+    err = row_error(Y, Yref, H.abs_matmul(X.astype(np.float64)))
+    assert err <= (1e-5 if f32 else 1e-12), err
+
+
+@pytest.mark.parametrize("k", [1, 8, 16])
+def test_spmm_integer_bitwise(k):
+    torch = torch_cuda()
+    A = int_matrix(2000, 25, seed=4)
+    ctx = upload(A, True)
+    X = np.random.default_rng(0).integers(-8, 9, size=(A.n, k)).astype(np.float32)
+    Y = ctx.spmm_sym(to_dev(X, np.float32)).cpu().numpy()
+    Yref = oracle.SymMatrix(A.n, A.row_ptr, A.col, A.val) @ X
+    assert np.array_equal(Y.astype(np.float64), Yref)
+
+
+def test_spmm_repeatable_and_no_alias():
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    A = int_matrix(1500, 30, seed=6)
+    ctx = upload(A, True)
+    X = to_dev(np.random.default_rng(1).integers(-8, 9, size=(A.n, 8)), np.float32)
+    Y1 = ctx.spmm_sym(X).cpu()
+    Y2 = ctx.spmm_sym(X).cpu()
+    assert torch.equal(Y1, Y2)
+    with pytest.raises(L.LobpcgError):
+        ctx.spmm_sym(X, X)
+    with pytest.raises(L.LobpcgError):
+        ctx.spmm_sym(to_dev(np.zeros((A.n, 17)), np.float32))
+
+
+@pytest.mark.parametrize("ka,kb", [(8, 8), (5, 13), (24, 48), (48, 48), (1, 1)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f64ctx"])
+def test_gram_parity(ka, kb, prec):
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    n = 5003  # several slabs of 16 rows, ragged tail
+    A = synth.random_sym(n, 2, seed=1)
+    f32 = prec != "f64ctx"
+    dt = np.float32 if f32 else np.float64
+    ctx = upload(A, f32)
+    a = synth.gaussian_block(n, ka, seed=2).astype(dt)
+    b = synth.gaussian_block(n, kb, seed=3).astype(dt)
+    p = {"f64": L.GRAM_F64, "f32": L.GRAM_F32, "bf16x3": L.GRAM_BF16X3, "f64ctx": L.GRAM_F64}[prec]
+    G = ctx.gram(to_dev(a, dt), to_dev(b, dt), prec=p).cpu().numpy()
+    ref = a.astype(np.float64).T @ b.astype(np.float64)
+    scale = np.sqrt(np.outer((a.astype(np.float64) ** 2).sum(0), (b.astype(np.float64) ** 2).sum(0)))
+    tol = {"f64": 1e-13, "f64ctx": 1e-13, "f32": 2e-6, "bf16x3": 2e-5}[prec]
+    err = np.max(np.abs(G - ref) / scale)
+    assert err <= tol, err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_gram_integer_exact(prec):
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    n = 1111
+    A = synth.random_sym(n, 2, seed=1)
+    ctx = upload(A, True)
+    rng = np.random.default_rng(5)
+    a = rng.integers(-16, 17, size=(n, 24)).astype(np.float32)
+    b = rng.integers(-16, 17, size=(n, 48)).astype(np.float32)
+    p = {"f64": L.GRAM_F64, "f32": L.GRAM_F32, "bf16x3": L.GRAM_BF16X3}[prec]
+    G = ctx.gram(to_dev(a, np.float32), to_dev(b, np.float32), prec=p).cpu().numpy()
+    assert np.array_equal(G, a.astype(np.float64).T @ b.astype(np.float64))
+
+
+@pytest.mark.parametrize("f32", [True, False])
+def test_precond_diag_parity(f32):
+    import paper_2109_00485_amd as L
+    from oracle.precond import diag_precond
+    torch = torch_cuda()
+    A = synth.random_sym(2000, 10, seed=8, f32=f32)
+    dt = np.float32 if f32 else np.float64
+    ctx = upload(A, f32)
+    gamma = ctx.query()["gamma"]
+    R = synth.gaussian_block(A.n, 8, seed=4).astype(dt)
+    # shifts chosen so that some d_i - theta_j fall inside the guard band
+    theta = np.array([A.diag[0], A.diag[10], -1.0, 5.0, A.diag[100] + 1e-9, 0.0, 100.0, A.diag[-1]])
+    W = ctx.precond_apply(to_dev(R, dt), to_dev(theta, np.float64), kind=L.PRECOND_DIAG).cpu().numpy()
+    ref = diag_precond(R.astype(np.float64), np.asarray(A.diag, dtype=dt).astype(np.float64), theta, 1e-5 * gamma)
+    rtol = 1e-6 if f32 else 1e-15
+    np.testing.assert_allclose(W, ref, rtol=rtol)
+    Wn = ctx.precond_apply(to_dev(R, dt), to_dev(theta, np.float64), kind=L.PRECOND_NONE).cpu().numpy()
+    assert np.array_equal(Wn, R)
+
+
+def test_gershgorin_matches_oracle():
+    torch = torch_cuda()
+    A = synth.zipf(3000, lmin=4, lmax=300, seed=3, f32=False)
+    ctx = upload(A, False)
+    H = oracle.SymMatrix.from_csr(A)
+    assert ctx.query()["gamma"] == pytest.approx(H.gershgorin(), rel=1e-13)
+    d = ctx.diag().cpu().numpy()
+    assert np.array_equal(d, A.diag)
+
+
+def test_create_rejects_malformed():
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    A = synth.random_sym(500, 5, seed=2, f32=False)
+
+    def try_create(rp, col, val):
+        class _A:
+            pass
+        a = _A()
+        a.n, a.row_ptr, a.col, a.val = A.n, rp, col, val
+        return L.Context.from_csr(a, dtype=L.F64)
+    # lower-triangle entry
+    col = A.col.copy()
+    col[A.row_ptr[10] + 1] = 3
+    with pytest.raises(L.LobpcgError) as e:
+        try_create(A.row_ptr, col, A.val)
+    assert e.value.status == L.EINVAL
+    # missing diagonal (first entry of row 20 replaced by its successor's column)
+    col = A.col.copy()
+    col[A.row_ptr[20]] = col[A.row_ptr[20] + 1] - 0 if A.row_ptr[21] - A.row_ptr[20] > 1 else 499
+    with pytest.raises(L.LobpcgError):
+        try_create(A.row_ptr, col, A.val)
+    # out-of-range column
+    col = A.col.copy()
+    col[A.row_ptr[5] + 1] = A.n + 7
+    with pytest.raises(L.LobpcgError):
+        try_create(A.row_ptr, col, A.val)
+    # row_ptr beyond nnz (must be rejected without reading out of bounds)
+    rp = A.row_ptr.copy()
+    rp[100] = A.nnz + 1000
+    with pytest.raises(L.LobpcgError):
+        try_create(rp, A.col, A.val)
+    # NaN value
+    val = A.val.copy()
+    val[17] = np.nan
+    with pytest.raises(L.LobpcgError) as e:
+        try_create(A.row_ptr, A.col, val)
+    assert e.value.status == L.ENONFINITE

@@ -1,0 +1,136 @@
+"""GPU LOBPCG (lobpcg_solve through the C ABI) against the FP64 oracle.
+
+Eigenvalue bar: |theta_j - lambda_j| <= 1e-6 * max(|lambda_j|, tau), with
+tau = 1e-3 * gamma the convergence floor; FP64 runs are also held to a pure
+relative 1e-8.  Invariants: orthonormal Ritz vectors, Ritz values that never
+increase (up to rounding), the residual certificate |theta - lambda| <= ||r||
+with the residual computed by the oracle's own product.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import torch_cuda, to_dev, upload
+from oracle.lobpcg import lobpcg as oracle_lobpcg
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+_ORACLE_CACHE = {}
+
+
+def oracle_solve(name, A, k=8, nev=5, **kw):
+    key = (name, k, nev, tuple(sorted(kw.items())))
+    if key not in _ORACLE_CACHE:
+        H = oracle.SymMatrix.from_csr(A)
+        _ORACLE_CACHE[key] = (H, oracle_lobpcg(H, W.initial_block(A.n, k, seed=1), nev, d=A.diag, **kw))
+    return _ORACLE_CACHE[key]
+
+
+def gpu_solve(A, f32, k=8, nev=5, **kw):
+    import paper_2109_00485_amd as L
+    ctx = upload(A, f32)
+    dt = np.float32 if f32 else np.float64
+    X = to_dev(W.initial_block(A.n, k, seed=1), dt)
+    r = ctx.solve(X, nev, **kw)
+    return ctx, r, X.cpu().numpy().astype(np.float64)
+
+
+def check_against_oracle(H, ref, r, Xg, f32, nev=5):
+    lam = ref.theta
+    tau = 1e-3 * H.gershgorin()
+    err = np.abs(r.evals[:nev] - lam)
+    assert np.all(err <= 1e-6 * np.maximum(np.abs(lam), tau)), (r.evals[:nev], lam)
+    # residual certificate with the oracle's product
+    R = H @ Xg[:, :nev] - Xg[:, :nev] * r.evals[:nev]
+    bound = np.linalg.norm(R, axis=0) / np.linalg.norm(Xg[:, :nev], axis=0)
+    assert np.all(err <= bound * 1.01 + 1e-12 * tau), (err, bound)
+    G = Xg.T @ Xg
+    assert np.abs(G - np.eye(G.shape[0])).max() < (2e-5 if f32 else 1e-10)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_random_sym_1k(f32):
+    A = W.make_matrix("random_sym_1k")
+    H, ref = oracle_solve("rs1k", A)
+    ctx, r, Xg = gpu_solve(A, f32, history=True, maxiter=2000)
+    assert r.status == 0, r
+    check_against_oracle(H, ref, r, Xg, f32)
+    if not f32:
+        np.testing.assert_allclose(r.evals[:5], ref.theta, rtol=1e-8)
+        # Ritz values never increase (Courant-Fischer), up to rounding
+        th = r.theta_hist
+        assert np.all(np.diff(th, axis=0) <= 1e-12 * r.gamma)
+        # same steps as the oracle: the first iterations' Ritz values agree closely
+        m = min(10, len(ref.theta_hist), th.shape[0])
+        np.testing.assert_allclose(th[:m], np.array(ref.theta_hist[:m]), rtol=1e-9, atol=1e-9)
+    else:
+        th = r.theta_hist
+        assert np.all(np.diff(th, axis=0) <= 1e-6 * r.gamma)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_random_sym_20k(f32):
+    A = W.make_matrix("random_sym_20k")
+    H, ref = oracle_solve("rs20k", A)
+    ctx, r, Xg = gpu_solve(A, f32, maxiter=5000)
+    assert r.status == 0, r
+    check_against_oracle(H, ref, r, Xg, f32)
+    assert r.confirmations >= 1
+
+
+def test_bf16x3_gram_solve():
+    import paper_2109_00485_amd as L
+    A = W.make_matrix("random_sym_20k")
+    H, ref = oracle_solve("rs20k", A)
+    val = np.asarray(A.val, dtype=np.float32)
+
+    class _A:
+        pass
+    a = _A()
+    a.n, a.row_ptr, a.col, a.val = A.n, A.row_ptr, A.col, val
+    ctx = L.Context.from_csr(a, dtype=L.F32, gram=L.GRAM_BF16X3)
+    X = to_dev(W.initial_block(A.n, 8, seed=1), np.float32)
+    r = ctx.solve(X, 5, maxiter=5000)
+    assert r.status == 0
+    check_against_oracle(H, ref, r, X.cpu().numpy().astype(np.float64), True)
+
+
+def test_laplacian_closed_form():
+    import paper_2109_00485_amd as L
+    n = 300
+    A = synth.laplacian_1d(n)
+    ctx = upload(A, False)
+    X = to_dev(W.initial_block(n, 8, seed=1), np.float64)
+    r = ctx.solve(X, 5, tol=1e-10, maxiter=5000, precond=L.PRECOND_NONE)
+    assert r.status == 0
+    j = np.arange(1, 6)
+    np.testing.assert_allclose(r.evals[:5], 2 - 2 * np.cos(j * np.pi / (n + 1)), rtol=1e-8)
+
+
+def test_diagonal_converges_immediately():
+    d = np.sort(np.random.default_rng(0).uniform(0, 10, 300))
+    A = synth.diagonal(d)
+    ctx = upload(A, False)
+    X0 = np.zeros((300, 8))
+    X0[np.arange(8), np.arange(8)[::-1]] = 1.0
+    r = ctx.solve(to_dev(X0, np.float64), 5)
+    assert r.status == 0 and r.iters == 0
+    np.testing.assert_allclose(r.evals[:5], d[:5], rtol=1e-15)
+
+
+def test_maxiter_and_argument_errors():
+    import paper_2109_00485_amd as L
+    A = W.make_matrix("random_sym_1k")
+    ctx = upload(A, False)
+    X = to_dev(W.initial_block(A.n, 8, seed=1), np.float64)
+    r = ctx.solve(X, 5, maxiter=3)
+    assert r.status == L.ENOCONV and r.iters == 3
+    assert np.all(np.isfinite(r.evals))
+    for bad in (dict(nev=9), dict(nev=0), dict(tol=0.0), dict(maxiter=-1)):
+        kw = dict(nev=5, tol=1e-6, maxiter=10)
+        kw.update(bad)
+        with pytest.raises(L.LobpcgError) as e:
+            ctx.solve(X, **kw)
+        assert e.value.status == L.EINVAL
