@@ -1,0 +1,114 @@
+"""Pins for the learned-preconditioner oracle (oracle.mlp): BF16 rounding
+against torch's own conversion, the forward pass against an independent
+torch.nn implementation, the zero-output special case (exactly the diagonal
+preconditioner), central finite differences of the group loss, the loss's
+invariances, and the closed form of a first Adam step."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-8, 8, 10000),
+                        # exact ties between two BF16 neighbours, both parities
+                        np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -(1.0 + 2 ** -8), 3.0 + 2 ** -7]),
+                        np.array([0.0, -0.0, 1.0, 65504.0])])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16_round(x), ref)
+
+
+def test_forward_matches_torch_nn():
+    p = mlp.init_params(3, mu=[100, -1, 30, 0.4], sigma=[50, 0.5, 5, 0.1])
+    rng = np.random.default_rng(1)
+    p.w3 = rng.standard_normal(64) * 0.1
+    p.b1 = rng.standard_normal(64) * 0.1
+    p.b2 = rng.standard_normal(64) * 0.1
+    p.b3 = 0.3
+    f = np.column_stack([rng.uniform(0, 200, 500), rng.uniform(-2, 0, 500), rng.uniform(20, 40, 500),
+                         rng.uniform(0.3, 0.5, 500)])
+    o, _ = mlp.forward(p, mlp.standardize(p, f))
+
+    def bf(a):
+        return torch.as_tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64)
+    l1, l2, l3 = torch.nn.Linear(4, 64).double(), torch.nn.Linear(64, 64).double(), torch.nn.Linear(64, 1).double()
+    with torch.no_grad():
+        l1.weight.copy_(bf(p.W1)); l1.bias.copy_(torch.from_numpy(p.b1))
+        l2.weight.copy_(bf(p.W2)); l2.bias.copy_(torch.from_numpy(p.b2))
+        l3.weight.copy_(bf(p.w3)[None, :]); l3.bias.fill_(p.b3)
+        z = (torch.from_numpy(f) - torch.tensor([100, -1, 30, 0.4.__float__()], dtype=torch.float64)) / \
+            torch.tensor([50, 0.5, 5, 0.1], dtype=torch.float64)
+        h1 = torch.relu(l1(z)).to(torch.float32).to(torch.bfloat16).to(torch.float64)
+        ref = l3(torch.relu(l2(h1)))[:, 0].numpy()
+    np.testing.assert_allclose(o, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_zero_output_is_diagonal():
+    p = mlp.init_params(0)
+    d = np.linspace(0, 10, 50)
+    theta = np.array([-1.0, 0.0, 2.5])
+    m = mlp.precond_scale(p, d, theta, np.ones(50), np.ones(50), eps=0.1)
+    assert np.array_equal(m, 1.0 / mlp.guard(d[:, None] - theta[None, :], 0.1))
+
+
+def synthetic_batch(seed, ngroups=6, per=40, k=3):
+    rng = np.random.default_rng(seed)
+    N = ngroups * per
+    gid = np.repeat(np.arange(ngroups), per)
+    feat = np.column_stack([rng.uniform(0, 200, N), rng.uniform(-2, 0, N), rng.uniform(20, 40, N),
+                            rng.uniform(0.3, 0.5, N)])
+    X = rng.standard_normal((N, k)) * 0.1
+    U = rng.standard_normal(N)
+    T = rng.standard_normal(N)
+    w = rng.uniform(0.5, 2.0, N)
+    return feat, U, T, w, X, gid, ngroups
+
+
+def test_group_loss_gradient_finite_differences():
+    p = mlp.init_params(5, mu=[100, -1, 30, 0.4], sigma=[60, 0.6, 6, 0.06])
+    rng = np.random.default_rng(2)
+    p.w3 = rng.standard_normal(64) * 0.2
+    p.b1 = rng.standard_normal(64) * 0.2
+    p.b2 = rng.standard_normal(64) * 0.2
+    batch = synthetic_batch(7)
+    L, g = mlp.group_loss(p, *batch, bf16=False)
+    h = 1e-6
+    for name, idx in (("W1", (3, 1)), ("W1", (10, 3)), ("b1", (5,)), ("W2", (7, 20)), ("W2", (63, 0)),
+                      ("b2", (11,)), ("w3", (9,)), ("w3", (40,)), ("b3", None)):
+        def loss_at(delta):
+            q = p.copy()
+            if idx is None:
+                q.b3 = p.b3 + delta
+            else:
+                arr = getattr(q, name)
+                arr[idx] += delta
+            return mlp.group_loss(q, *batch, with_grad=False, bf16=False)[0]
+        fd = (loss_at(h) - loss_at(-h)) / (2 * h)
+        an = g[name] if idx is None else g[name][idx]
+        assert an == pytest.approx(fd, rel=1e-5, abs=1e-9), (name, idx, an, fd)
+
+
+def test_group_loss_invariances():
+    p = mlp.init_params(1)
+    feat, U, T, w, X, gid, ng = synthetic_batch(3)
+    L1, _ = mlp.group_loss(p, feat, U, T, w, X, gid, ng, with_grad=False)
+    L2, _ = mlp.group_loss(p, feat, 7.5 * U, -3.0 * T, w, X, gid, ng, with_grad=False)
+    assert L1 == pytest.approx(L2, rel=1e-12)
+    assert 0.0 <= L1 <= 1.0
+    # a direction equal to the target (with nothing in span(X)) has zero loss
+    X0 = np.zeros_like(X)
+    L0, _ = mlp.group_loss(p, feat, T.copy(), T, w, X0, gid, ng, with_grad=False)
+    assert abs(L0) < 1e-14
+
+
+def test_first_adam_step_closed_form():
+    p = mlp.init_params(2)
+    g = {k: np.asarray(getattr(p, k), dtype=np.float64) * 0 + 0.3 for k in mlp.Params.NAMES}
+    g["W1"] = np.full_like(p.W1, -2.0)
+    st = mlp.adam_init(p)
+    q = mlp.adam_step(p, g, st, lr=1e-2)
+    # bias-corrected first step moves every weight by -lr * g / (|g| + eps)
+    np.testing.assert_allclose(q.W1 - p.W1, 1e-2 * 2.0 / (2.0 + 1e-8), rtol=1e-12)
+    np.testing.assert_allclose(q.W2 - p.W2, -1e-2 * 0.3 / (0.3 + 1e-8), rtol=1e-12)
