@@ -35,11 +35,24 @@ def cholesky_upper(B: np.ndarray) -> np.ndarray:
     return L.T.copy()
 
 
-def cholqr(W: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
-    """Cholesky QR: returns (W R^{-1}, R).  Raises NotSPD when W^T W is not SPD."""
+def cholqr(W: np.ndarray, shift: float | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """Cholesky QR: returns (W R^{-1}, R).  Raises NotSPD when W^T W is not SPD.
+
+    With ``shift``, the Gram matrix is first scaled to unit diagonal,
+    B' = S B S with S = diag(B)^{-1/2}, and B' + shift*I is factored (shifted
+    Cholesky QR, Fukaya et al. 2020); then R = R' S^{-1}.
+    """
     B = gram(W, W)
     B = 0.5 * (B + B.T)
-    R = cholesky_upper(B)
+    if shift is None:
+        R = cholesky_upper(B)
+    else:
+        dg = np.diag(B)
+        if np.any(dg <= 0):
+            raise NotSPD("zero column")
+        s = 1.0 / np.sqrt(dg)
+        Rp = cholesky_upper(B * np.outer(s, s) + shift * np.eye(B.shape[0]))
+        R = Rp / s[None, :]
     Q = sla.solve_triangular(R, np.asarray(W, dtype=np.float64).T, trans="T", lower=False).T
     return Q, R
 

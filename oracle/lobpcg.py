@@ -20,8 +20,9 @@ Readings where the paper is silent (each is shared by the HIP path):
     recomputed by an explicit product, theta_j = x_j^T H x_j, and the test is
     repeated (guards the drift of the eqs. upd1-upd2 recurrences);
   * W is orthogonalised against X (W <- W - X (X^T W)) and then put through
-    Cholesky QR (Section 3.5); if Cholesky QR fails the projection is
-    repeated once, then the solve stops with "not SPD";
+    Cholesky QR (Section 3.5); if the Cholesky factor fails, the Gram matrix
+    is scaled to unit diagonal and shifted by 1e-12 (shifted Cholesky QR),
+    and only if that fails too the solve stops with "not SPD";
   * P and H P are scaled column-wise by 1/||P_j|| after each update;
   * if O = S^T S is not positive definite, P is dropped for that iteration;
   * the preconditioner is the diagonal shift-inverse (oracle.precond) unless a
@@ -57,6 +58,7 @@ class Result:
     rel_hist: list = field(default_factory=list)
     resid_hist: list = field(default_factory=list)
     p_dropped: int = 0
+    cholqr_shifts: int = 0
 
 
 def rel_residuals(R: np.ndarray, X: np.ndarray, theta: np.ndarray, tau: float) -> np.ndarray:
@@ -140,19 +142,18 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
         W = np.asarray(apply_k(R, theta, X), dtype=np.float64)
         if callback is not None:
             callback(it, X, R, theta, W)
-        # orthogonalise against X, then Cholesky QR (Section 3.5)
-        ok = False
-        for _attempt in range(2):
-            W = W - X @ gram(X, W)
+        # orthogonalise against X, then Cholesky QR (Section 3.5); a shifted
+        # Cholesky QR is the fallback when W^T W is numerically singular
+        W = W - X @ gram(X, W)
+        try:
+            W, _ = cholqr(W)
+        except NotSPD:
             try:
-                W, _ = cholqr(W)
-                ok = True
-                break
+                W, _ = cholqr(W, shift=1e-12)
+                res.cholqr_shifts += 1
             except NotSPD:
-                continue
-        if not ok:
-            res.status = ENOTSPD
-            break
+                res.status = ENOTSPD
+                break
         HW = H @ W
         n_spmm += 1
         # lines 7-8: Rayleigh-Ritz on S = [X, W, P]

@@ -159,7 +159,7 @@ int build_csr(lobpcg_ctx *ctx, const int64_t *rp, const int32_t *col, const void
 
 void free_ctx(lobpcg_ctx *c) {
     if (!c) return;
-    void *ptrs[] = {c->rp, c->ci, c->val, c->diag, c->feat_rownorm, c->feat_tilemean, c->X, c->W, c->P,
+    void *ptrs[] = {c->rp, c->ci, c->val, c->diag, c->cp, c->cri, c->cval, c->feat_rownorm, c->feat_tilemean, c->X, c->W, c->P,
                     c->HX, c->HW, c->HP, c->gram_partial, c->gram_out, c->gram_out2, c->rr_C, c->rr_theta,
                     c->orth_rinv, c->norm_partial, c->report_dev, c->dflags, c->tiled.tile_nnz_off,
                     c->tiled.tile_col, c->tiled.tile_row, c->tiled.ent_rc, c->tiled.ent_val,
@@ -175,6 +175,7 @@ void free_ctx(lobpcg_ctx *c) {
 }  // namespace
 
 int build_tiled_format(lobpcg_ctx *ctx, hipStream_t s);  // spmm.hip
+int build_column_view(lobpcg_ctx *ctx, hipStream_t s);
 int tiled_format_worthwhile(lobpcg_ctx *ctx, hipStream_t s, int *yes);
 
 extern "C" void lobpcg_opts_default(lobpcg_opts *o) {
@@ -294,6 +295,8 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
 
     int rc = o.dtype == LOBPCG_F32 ? build_csr<float>(ctx, row_ptr, col, val, s)
                                    : build_csr<double>(ctx, row_ptr, col, val, s);
+    if (rc != LOBPCG_OK) return fail(rc);
+    rc = build_column_view(ctx, s);
     if (rc != LOBPCG_OK) return fail(rc);
 
     ctx->format = LOBPCG_FORMAT_CSR;

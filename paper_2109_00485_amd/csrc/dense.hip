@@ -51,7 +51,7 @@ __device__ bool chol_lower(double *a, int N, double tol) {
 }
 
 __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__restrict__ B, double *__restrict__ rinv,
-                                                     int *__restrict__ flags, double tol) {
+                                                     int *__restrict__ flags, double tol, double shift) {
     __shared__ double a[NMAX * LD];
     __shared__ double sc[NMAX];
     const int t = threadIdx.x;
@@ -74,6 +74,16 @@ __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__rest
     }
     __syncthreads();
     bool ok = posdiag && chol_lower(a, k, tol);
+    if (posdiag && !ok) {
+        // shifted Cholesky QR: factor B' + shift I (B' has unit diagonal)
+        for (int e = t; e < k * k; e += LOBPCG_WAVE) {
+            int i = e / k, j = e % k;
+            a[i * LD + j] = 0.5 * (B[i * k + j] + B[j * k + i]) * sc[i] * sc[j] + (i == j ? shift : 0.0);
+        }
+        __syncthreads();
+        ok = chol_lower(a, k, tol);
+        if (ok && t == 0) atomicOr(&flags[0], FLAG_CHOLQR_SHIFT);
+    }
     if (!ok) {
         if (t == 0) atomicOr(&flags[0], FLAG_CHOLQR_FAIL);
         return;
@@ -309,7 +319,8 @@ __global__ void rayleigh_quotient_kernel(int k, const double *__restrict__ M, do
 }  // namespace
 
 int launch_cholinv(lobpcg_ctx *ctx, int k, const double *B, double *rinv, hipStream_t s) {
-    cholinv_kernel<<<1, 64, 0, s>>>(k, B, rinv, ctx->dflags, 1e-14);
+    const double shift = ctx->dtype == LOBPCG_F64 ? 1e-12 : 1e-6;
+    cholinv_kernel<<<1, 64, 0, s>>>(k, B, rinv, ctx->dflags, 1e-14, shift);
     return LOBPCG_OK;
 }
 

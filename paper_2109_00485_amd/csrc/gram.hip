@@ -14,7 +14,8 @@
 //
 // MFMA operand layout used (16x16xK, wave64): lane l supplies
 // A[i = l % 16][kk] and B[kk][j = l % 16] for the kk owned by lane group l / 16;
-// the four outputs of lane l are D[4 * (l / 16) + r][l % 16], r = 0..3.
+// the four outputs of lane l are D[4 * (l / 16) + r][l % 16], r = 0..3, for the
+// FP32-accumulating instructions and D[l / 16 + 4 * r][l % 16] for the FP64 one.
 #include "internal.hpp"
 
 namespace {
@@ -153,7 +154,9 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
     for (int e = threadIdx.x; e < MT * NT * 4 * LOBPCG_WAVE; e += GRAM_THREADS) {
         int l = e % LOBPCG_WAVE, r = (e / LOBPCG_WAVE) % 4, tile = e / (4 * LOBPCG_WAVE);
         int i = tile / NT, j = tile % NT;
-        int m = 16 * i + 4 * (l / 16) + r, nn = 16 * j + (l % 16);
+        // output rows of lane l: FP32 MFMA holds 4*(l/16)+r, FP64 MFMA holds (l/16)+4*r
+        int m = MODE == M_F64 ? 16 * i + (l / 16) + 4 * r : 16 * i + 4 * (l / 16) + r;
+        int nn = 16 * j + (l % 16);
         if (m < KA && nn < KB) out[m * KB + nn] = red[e];
     }
 }

@@ -21,6 +21,7 @@ enum : int {
     FLAG_CHOLQR_FAIL = 32,   // Cholesky of W^T W failed; later kernels of the iteration skip
     FLAG_RR_FAIL = 64,       // Rayleigh-Ritz failed even without P
     FLAG_RR_PDROP = 128,     // Rayleigh-Ritz dropped P this iteration
+    FLAG_CHOLQR_SHIFT = 256, // Cholesky QR needed the diagonal shift
 };
 
 // Per-iteration report copied to the host (doubles, padded to kmax).
@@ -58,6 +59,10 @@ struct lobpcg_ctx {
     int32_t *ci = nullptr;
     void *val = nullptr;
     void *diag = nullptr;
+    // the same strict upper triangle in column order (CSC): the transposed traversal
+    int64_t *cp = nullptr;
+    int32_t *cri = nullptr;
+    void *cval = nullptr;
     TiledFormat tiled;
     // MLP features (float): full-row off-diagonal 1-norm and 64-row tile mean |h|
     float *feat_rownorm = nullptr, *feat_tilemean = nullptr;

@@ -13,6 +13,7 @@
 // nev wanted columns; then H X is recomputed explicitly, theta_j becomes the
 // Rayleigh quotient x_j^T H x_j / x_j^T x_j, and the test is repeated.
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "internal.hpp"
@@ -123,6 +124,9 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
 
     std::vector<double> rel(k);
     bool finite = true;
+    // optional progress trace on stderr: LOBPCG_TRACE=<every n iterations>
+    const char *tr = getenv("LOBPCG_TRACE");
+    const int trace_every = tr ? std::max(1, atoi(tr)) : 0;
     bool have_p = false;
     int it = 0;
     int status = LOBPCG_ENOCONV;
@@ -208,6 +212,15 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             done_iter = true;
         }
         if (!done_iter) { status = set_err(ctx, LOBPCG_ENOTSPD, "Cholesky QR failed twice at iteration %d", it); break; }
+        if (trace_every && it % trace_every == 0) {
+            rel_from_report(ctx, k, tau, rel.data(), &finite);
+            fprintf(stderr, "[lobpcg] it %5d flags 0x%03x nblk %d theta", it, (int)ctx->report_host->flags,
+                    (int)ctx->report_host->nblk_used);
+            for (int j = 0; j < nev; ++j) fprintf(stderr, " %.9g", ctx->report_host->theta[j]);
+            fprintf(stderr, " rel");
+            for (int j = 0; j < k; ++j) fprintf(stderr, " %.2e", rel[j]);
+            fprintf(stderr, "\n");
+        }
         if (info && info->theta_hist && info->rel_hist) {
             rel_from_report(ctx, k, tau, rel.data(), &finite);
             for (int j = 0; j < k; ++j) {

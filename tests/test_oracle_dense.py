@@ -92,3 +92,19 @@ def test_diag_precond_closed_form():
     expect[0, 1] = 1 / -1.0
     np.testing.assert_allclose(W, expect, rtol=1e-15)
     np.testing.assert_array_equal(guard(np.array([0.0, -0.1, 0.1, -2.0]), 0.5), [0.5, -0.5, 0.5, -2.0])
+
+
+def test_shifted_cholqr():
+    W = synth.gaussian_block(400, 6, seed=9)
+    W = np.hstack([W, W[:, :1] * (1 + 1e-15)])   # numerically dependent column
+    with pytest.raises(NotSPD):
+        cholqr(W)
+    Q, R = cholqr(W, shift=1e-12)
+    np.testing.assert_allclose(Q @ R, W, atol=1e-10)
+    # the well-conditioned part stays orthonormal
+    np.testing.assert_allclose(Q[:, :6].T @ Q[:, :6], np.eye(6), atol=1e-8)
+    # the shift is a no-op for a well-conditioned block (up to the shift itself)
+    W2 = synth.gaussian_block(400, 5, seed=10)
+    Q1, _ = cholqr(W2)
+    Q2, _ = cholqr(W2, shift=1e-12)
+    np.testing.assert_allclose(Q1, Q2, atol=1e-10)
