@@ -47,7 +47,7 @@ extern "C" {
 #define LOBPCG_F32 1             /* FP32 values, blocks and sparse arithmetic   */
 #define LOBPCG_F64 2             /* FP64 everywhere                             */
 
-#define LOBPCG_GRAM_AUTO   0     /* FP64 for F64 contexts, FP32 MFMA for F32    */
+#define LOBPCG_GRAM_AUTO   0     /* FP64 MFMA (on the FP32 values for F32 contexts) */
 #define LOBPCG_GRAM_F64    1     /* inputs upcast to FP64, FP64 MFMA            */
 #define LOBPCG_GRAM_F32    2     /* FP32 MFMA, FP64 reduction across workgroups */
 #define LOBPCG_GRAM_BF16X3 3     /* split-BF16 (a0b0 + a0b1 + a1b0) MFMA, FP32 inputs */
@@ -79,6 +79,7 @@ typedef struct {
     int p_dropped;        /* iterations whose Rayleigh-Ritz dropped P           */
     int cholqr_retries;   /* Cholesky QR retries after re-projection            */
     int confirmations;    /* explicit H X recomputations on apparent convergence */
+    int refreshes;        /* periodic explicit recomputations of H X and H P     */
     int status;           /* same value the call returned                       */
     double gamma;         /* Gershgorin bound max_i sum_j |H_ij|                 */
     /* optional, caller-owned host arrays of maxiter*k doubles (NULL to skip):
@@ -165,6 +166,7 @@ int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B, int kb, d
  *   info     host, may be NULL
  * The run ends when the nev wanted columns meet tol and an explicit product
  * H X confirms it (the recurrences eqs. upd1-upd2 drift in finite precision).
+ * F32 contexts also recompute H X and H P explicitly every 20 iterations.
  * Returns LOBPCG_ENOCONV when maxiter is reached (X and evals still written).
  */
 int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *X, double *evals, double *rel, double tol,

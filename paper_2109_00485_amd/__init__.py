@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("n_spmm", ctypes.c_int), ("p_dropped", ctypes.c_int),
-                ("cholqr_retries", ctypes.c_int), ("confirmations", ctypes.c_int), ("status", ctypes.c_int),
+                ("cholqr_retries", ctypes.c_int), ("confirmations", ctypes.c_int), ("refreshes", ctypes.c_int),
+                ("status", ctypes.c_int),
                 ("gamma", ctypes.c_double),
                 ("theta_hist", ctypes.POINTER(ctypes.c_double)), ("rel_hist", ctypes.POINTER(ctypes.c_double)),
                 ("timing", ctypes.c_int),
@@ -119,6 +120,7 @@ class SolveResult:
     p_dropped: int
     cholqr_retries: int
     confirmations: int
+    refreshes: int
     gamma: float
     times: dict = field(default_factory=dict)
     theta_hist: Optional[np.ndarray] = None
@@ -242,7 +244,7 @@ class Context:
             self._check(rc, "solve")
         res = SolveResult(evals=evals, rel=rel, status=rc, iters=info.iters, n_spmm=info.n_spmm,
                           p_dropped=info.p_dropped, cholqr_retries=info.cholqr_retries,
-                          confirmations=info.confirmations, gamma=info.gamma,
+                          confirmations=info.confirmations, refreshes=info.refreshes, gamma=info.gamma,
                           times=dict(spmm=info.t_spmm, precond_update=info.t_precond_update, gram=info.t_gram,
                                      rr=info.t_rr, orth=info.t_orth, total=info.t_total))
         if history:

@@ -161,9 +161,8 @@ void free_ctx(lobpcg_ctx *c) {
     if (!c) return;
     void *ptrs[] = {c->rp, c->ci, c->val, c->diag, c->cp, c->cri, c->cval, c->feat_rownorm, c->feat_tilemean, c->X, c->W, c->P,
                     c->HX, c->HW, c->HP, c->gram_partial, c->gram_out, c->gram_out2, c->rr_C, c->rr_theta,
-                    c->orth_rinv, c->norm_partial, c->report_dev, c->dflags, c->tiled.tile_nnz_off,
-                    c->tiled.tile_col, c->tiled.tile_row, c->tiled.ent_rc, c->tiled.ent_val,
-                    c->tiled.work_tile0};
+                    c->orth_rinv, c->norm_partial, c->report_dev, c->dflags, c->tiled.rix, c->tiled.cix,
+                    c->tiled.rlist_off, c->tiled.rlist, c->tiled.clist_off, c->tiled.clist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->report_host) (void)hipHostFree(c->report_host);
@@ -174,9 +173,7 @@ void free_ctx(lobpcg_ctx *c) {
 
 }  // namespace
 
-int build_tiled_format(lobpcg_ctx *ctx, hipStream_t s);  // spmm.hip
-int build_column_view(lobpcg_ctx *ctx, hipStream_t s);
-int tiled_format_worthwhile(lobpcg_ctx *ctx, hipStream_t s, int *yes);
+int build_column_view(lobpcg_ctx *ctx, hipStream_t s);  // spmm.hip
 
 extern "C" void lobpcg_opts_default(lobpcg_opts *o) {
     if (!o) return;
@@ -229,7 +226,10 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
     ctx->dtype = o.dtype;
     ctx->esz = o.dtype == LOBPCG_F32 ? 4 : 8;
     ctx->kmax = o.kmax;
-    ctx->gram = o.gram == LOBPCG_GRAM_AUTO ? (o.dtype == LOBPCG_F64 ? LOBPCG_GRAM_F64 : LOBPCG_GRAM_F32) : o.gram;
+    // FP32 blocks: FP64 accumulation of the exact FP32 products by default (an FP32
+    // accumulation leaves the residual floor of the solve above 1e-6)
+    ctx->gram = o.gram == LOBPCG_GRAM_AUTO ? LOBPCG_GRAM_F64 : o.gram;
+    ctx->refresh_every = o.dtype == LOBPCG_F32 ? 20 : 0;
     ctx->tile = o.tile;
     ctx->tau_rel = o.tau_rel;
     ctx->eps_rel = o.eps_rel;
@@ -296,24 +296,10 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
     int rc = o.dtype == LOBPCG_F32 ? build_csr<float>(ctx, row_ptr, col, val, s)
                                    : build_csr<double>(ctx, row_ptr, col, val, s);
     if (rc != LOBPCG_OK) return fail(rc);
+    ctx->format = LOBPCG_FORMAT_CSR;
+    ctx->format_request = o.format;
     rc = build_column_view(ctx, s);
     if (rc != LOBPCG_OK) return fail(rc);
-
-    ctx->format = LOBPCG_FORMAT_CSR;
-    if (o.format != LOBPCG_FORMAT_CSR && o.dtype == LOBPCG_F32) {
-        int yes = o.format == LOBPCG_FORMAT_TILED;
-        if (!yes) {
-            rc = tiled_format_worthwhile(ctx, s, &yes);
-            if (rc != LOBPCG_OK) return fail(rc);
-        }
-        if (yes) {
-            rc = build_tiled_format(ctx, s);
-            if (rc != LOBPCG_OK) return fail(rc);
-            ctx->format = LOBPCG_FORMAT_TILED;
-        }
-    } else if (o.format == LOBPCG_FORMAT_TILED) {
-        return fail(LOBPCG_EUNSUPPORTED);
-    }
     if (hipStreamSynchronize(s) != hipSuccess) return fail(LOBPCG_EHIP);
     *out = ctx;
     return LOBPCG_OK;

@@ -34,25 +34,25 @@ struct Report {
     double pad[6];
 };
 
-// Tiled format descriptor (tile-row ordered; see spmm.hip).
+// Compressed-index (tiled) form of the two traversals: 16-bit
+// (slot << 6 | local index) per entry, with per-tile-row lists of the 64-wide
+// tile columns (row view) and tile rows (column view) the slots refer to.
 struct TiledFormat {
-    int64_t ntiles = 0;        // stored off-diagonal-or-diagonal tiles
-    int64_t ntilerows = 0;
-    int64_t *tile_nnz_off = nullptr;   // ntiles+1 offsets into the entry arrays
-    int32_t *tile_col = nullptr;       // tile column index J per tile
-    int32_t *tile_row = nullptr;       // tile row index I per tile
-    uint16_t *ent_rc = nullptr;        // packed (r | c << 8) local coordinates
-    void *ent_val = nullptr;           // values (context dtype)
-    int64_t nent = 0;
-    int32_t *work_tile0 = nullptr;     // per work item: first tile
-    int64_t nwork = 0;
+    int64_t ntilerows = 0, nslots_row = 0, nslots_col = 0;
+    uint16_t *rix = nullptr;       // row view, aligned with the CSR entries
+    uint16_t *cix = nullptr;       // column view, aligned with the CSC entries
+    int32_t *rlist_off = nullptr;  // ntilerows+1
+    int32_t *rlist = nullptr;      // tile-column index per row-view slot
+    int32_t *clist_off = nullptr;  // ntilerows+1
+    int32_t *clist = nullptr;      // tile-row index per column-view slot
 };
 
 struct lobpcg_ctx {
     int64_t n = 0, nnz = 0, nnz_off = 0;
-    int dtype = LOBPCG_F32, format = LOBPCG_FORMAT_CSR, tile = 64, kmax = 16, gram = LOBPCG_GRAM_AUTO;
+    int dtype = LOBPCG_F32, format = LOBPCG_FORMAT_CSR, format_request = LOBPCG_FORMAT_AUTO, tile = 64, kmax = 16, gram = LOBPCG_GRAM_AUTO;
     size_t esz = 4;
     double tau_rel = 1e-3, eps_rel = 1e-5, gamma = 0.0;
+    int refresh_every = 0;  // explicit H X, H P recomputation period (0 = only on apparent convergence)
     int device = 0;
     // strict upper triangle in CSR + diagonal
     int64_t *rp = nullptr;

@@ -77,7 +77,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     const bool timing = info && info->timing;
     Timer tm{ctx, s, timing};
     double t_spmm = 0, t_upd = 0, t_gram = 0, t_rr = 0, t_orth = 0;
-    int n_spmm = 0, p_dropped = 0, retries = 0, confirmations = 0;
+    int n_spmm = 0, p_dropped = 0, retries = 0, confirmations = 0, refreshes = 0;
     const int upd_precond = precond == LOBPCG_PRECOND_MLP ? LOBPCG_PRECOND_NONE : precond;
     auto apply_mlp = [&]() -> int {
         if (precond == LOBPCG_PRECOND_MLP) return launch_mlp_precond(ctx, ctx->W, ctx->rr_theta, ctx->W, k, s);
@@ -147,7 +147,8 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             g.b[0] = ctx->X;
             g.b[1] = ctx->HX;
             g.na = 1; g.nb = 2; g.wa = g.wb = k;
-            TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out, s));
+            // the reported Ritz values: Rayleigh quotients with FP64 accumulation
+            TRY(launch_gram(ctx, g, LOBPCG_GRAM_F64, ctx->gram_out, s));
             TRY(launch_rayleigh_quotients(ctx, k, s));
             tm.mark(2);
             TRY(launch_update(ctx, k, 0, upd_precond, 1, s));
@@ -212,6 +213,20 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             done_iter = true;
         }
         if (!done_iter) { status = set_err(ctx, LOBPCG_ENOTSPD, "Cholesky QR failed twice at iteration %d", it); break; }
+        if (ctx->refresh_every && it % ctx->refresh_every == 0) {
+            // the recurrences eqs. upd1-upd2 drift in FP32: recompute H X and H P
+            tm.mark(0);
+            TRY(launch_spmm(ctx, ctx->X, ctx->HX, k, s));
+            TRY(launch_spmm(ctx, ctx->P, ctx->HP, k, s));
+            n_spmm += 2;
+            ++refreshes;
+            tm.mark(1);
+            TRY(launch_update(ctx, k, 0, upd_precond, 1, s));
+            TRY(apply_mlp());
+            tm.mark(2);
+            TRY(read_report(ctx, s));
+            t_spmm += tm.span(0, 1); t_upd += tm.span(1, 2);
+        }
         if (trace_every && it % trace_every == 0) {
             rel_from_report(ctx, k, tau, rel.data(), &finite);
             fprintf(stderr, "[lobpcg] it %5d flags 0x%03x nblk %d theta", it, (int)ctx->report_host->flags,
@@ -243,6 +258,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
         info->p_dropped = p_dropped;
         info->cholqr_retries = retries;
         info->confirmations = confirmations;
+        info->refreshes = refreshes;
         info->status = status;
         info->gamma = ctx->gamma;
         info->t_spmm = t_spmm;

@@ -10,7 +10,7 @@ def torch_cuda():
     return torch
 
 
-def upload(A, f32: bool):
+def upload(A, f32: bool, fmt=None, **kw):
     """Context for the upper-triangle CSR ``A`` (values cast to the context dtype)."""
     import paper_2109_00485_amd as L
     torch = torch_cuda()
@@ -20,7 +20,7 @@ def upload(A, f32: bool):
         pass
     a = _A()
     a.n, a.row_ptr, a.col, a.val = A.n, A.row_ptr, A.col, val
-    return L.Context.from_csr(a, dtype=L.F32 if f32 else L.F64)
+    return L.Context.from_csr(a, dtype=L.F32 if f32 else L.F64, fmt=L.FORMAT_AUTO if fmt is None else fmt, **kw)
 
 
 def to_dev(x, dtype):

@@ -37,11 +37,14 @@ MATRICES = {
 @pytest.mark.parametrize("name", list(MATRICES))
 @pytest.mark.parametrize("k", [1, 5, 8, 16])
 @pytest.mark.parametrize("f32", [True, False])
-def test_spmm_parity(name, k, f32):
+@pytest.mark.parametrize("fmt", ["csr", "tiled"])
+def test_spmm_parity(name, k, f32, fmt):
+    import paper_2109_00485_amd as L
     torch = torch_cuda()
     A = MATRICES[name]()
     dt = np.float32 if f32 else np.float64
-    ctx = upload(A, f32)
+    ctx = upload(A, f32, fmt={"csr": L.FORMAT_CSR, "tiled": L.FORMAT_TILED}[fmt])
+    assert ctx.query()["format"] == (L.FORMAT_CSR if fmt == "csr" else L.FORMAT_TILED)
     X = synth.gaussian_block(A.n, k, seed=17).astype(dt)
     Y = ctx.spmm_sym(to_dev(X, dt)).cpu().numpy()
     H = oracle.SymMatrix(A.n, A.row_ptr, A.col, np.asarray(A.val, dtype=dt))
@@ -51,14 +54,38 @@ def test_spmm_parity(name, k, f32):
 
 
 @pytest.mark.parametrize("k", [1, 8, 16])
-def test_spmm_integer_bitwise(k):
+@pytest.mark.parametrize("fmt", ["csr", "tiled"])
+def test_spmm_integer_bitwise(k, fmt):
+    import paper_2109_00485_amd as L
     torch = torch_cuda()
     A = int_matrix(2000, 25, seed=4)
-    ctx = upload(A, True)
+    ctx = upload(A, True, fmt={"csr": L.FORMAT_CSR, "tiled": L.FORMAT_TILED}[fmt])
     X = np.random.default_rng(0).integers(-8, 9, size=(A.n, k)).astype(np.float32)
     Y = ctx.spmm_sym(to_dev(X, np.float32)).cpu().numpy()
     Yref = oracle.SymMatrix(A.n, A.row_ptr, A.col, A.val) @ X
     assert np.array_equal(Y.astype(np.float64), Yref)
+
+
+def test_format_choice():
+    """AUTO picks 16-bit tile indices when every 64-row tile-row touches at most
+    1023 tile columns, 32-bit indices otherwise; forcing TILED then fails cleanly."""
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    A = synth.tiled(64 * 200, tile_draws=20, p=0.05, seed=3)
+    assert upload(A, True).query()["format"] == L.FORMAT_TILED
+    B = synth.random_sym(200_000, 50, seed=3, f32=True)   # ~6400 tile columns per tile-row
+    assert upload(B, True).query()["format"] == L.FORMAT_CSR
+    with pytest.raises(L.LobpcgError) as e:
+        upload(B, True, fmt=L.FORMAT_TILED)
+    assert e.value.status == L.EUNSUPPORTED
+    # the CSR result on the wide matrix still matches the oracle at sampled rows
+    ctx = upload(B, True)
+    X = synth.gaussian_block(B.n, 8, seed=2).astype(np.float32)
+    Y = ctx.spmm_sym(to_dev(X, np.float32)).cpu().numpy()
+    H = oracle.SymMatrix.from_csr(B)
+    rows = np.random.default_rng(0).choice(B.n, 2000, replace=False)
+    Yr, Ya = H.rows(X.astype(np.float64), rows)
+    assert row_error(Y[rows], Yr, Ya) <= 1e-5
 
 
 def test_spmm_repeatable_and_no_alias():
