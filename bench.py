@@ -78,6 +78,10 @@ def main():
     ap.add_argument("--maxiter", type=int, default=5000)
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="only time the sparse product (profiling runs); prints one JSON line")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="with --spmm-only: also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -115,6 +119,21 @@ def main():
     torch.cuda.synchronize()
     spmm_ms = s0.elapsed_time(s1) / args.spmm_reps
     log(f"standalone spmm: {spmm_ms:.3f} ms, {nbytes / spmm_ms / 1e6:.1f} GB/s")
+    if args.spmm_only:
+        out = {"mode": "spmm-only", "workload": args.workload, "k": args.k, "reps": args.spmm_reps,
+               "spmm_ms": round(spmm_ms, 4), "gbs": round(nbytes / spmm_ms / 1e6, 2), "bytes": int(nbytes)}
+        if args.copy_calibration:
+            # a plain streaming kernel of known size: reads 1 GiB, writes 1 GiB
+            a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            a.fill_(1.0)
+            torch.cuda.synchronize()
+            for _ in range(3):
+                torch.mul(a, 2.0, out=b)
+            torch.cuda.synchronize()
+            out["copy_bytes_each_way"] = a.numel() * 4
+        print(json.dumps(out), flush=True)
+        return
 
     def step():
         X = X0.clone()

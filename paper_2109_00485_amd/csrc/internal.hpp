@@ -37,8 +37,10 @@ struct Report {
 // Compressed-index (tiled) form of the two traversals: 16-bit
 // (slot << 6 | local index) per entry, with per-tile-row lists of the 64-wide
 // tile columns (row view) and tile rows (column view) the slots refer to.
+// Every row segment is padded to a multiple of 8 entries; the context's
+// rp/cp/val/cval then describe the padded views.
 struct TiledFormat {
-    int64_t ntilerows = 0, nslots_row = 0, nslots_col = 0;
+    int64_t ntilerows = 0, nslots_row = 0, nslots_col = 0, nent_row = 0, nent_col = 0;
     uint16_t *rix = nullptr;       // row view, aligned with the CSR entries
     uint16_t *cix = nullptr;       // column view, aligned with the CSC entries
     int32_t *rlist_off = nullptr;  // ntilerows+1

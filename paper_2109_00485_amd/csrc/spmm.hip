@@ -158,20 +158,44 @@ __global__ __launch_bounds__(SPMM_THREADS) void spmm_pull_kernel(
 // the workgroup stages the 64-row blocks of X that the window's slots refer to
 // into LDS with coalesced 16-byte loads (each X block is fetched once per
 // tile-row, not once per entry), then each lane consumes its entries whose
-// slot falls in the window, BATCH at a time: the batch's index and value
-// loads are issued together and the entries past the window are read again
-// (from cache) in the next window.  Within a lane the entries are sorted by
-// slot, so the consumed entries of a batch are always a prefix.
+// slot falls in the window.  Row segments are padded to whole 8-entry chunks;
+// chunk m of a segment belongs to lane m % 8, which reads it with one 16-byte
+// index load and two 16-byte value loads; a chunk that straddles a window
+// boundary is read again (from cache) in the next window.  Entries are sorted
+// by slot, so what a lane consumes of a chunk is always a contiguous run.
+#ifndef LOBPCG_TW_LDS
+#define LOBPCG_TW_LDS 0         // bytes of LDS for staged X blocks per workgroup (0: by block width)
+#endif
+#ifndef LOBPCG_TW_DB
+#define LOBPCG_TW_DB 0          // double-buffer the X windows
+#endif
 constexpr int TW_THREADS = 512;
-constexpr int BATCH = 8;
+constexpr int NBUF = LOBPCG_TW_DB ? 2 : 1;
 
 template <typename T, int KP>
 struct TwShape {
     static constexpr int PAD = 16 / (int)sizeof(T);   // 16-byte pad: keeps row alignment, spreads banks
     static constexpr int STRIDE = KP + PAD;
     static constexpr int SLOT = 64 * STRIDE;           // elements per staged 64-row block
-    static constexpr int WT = (32768 / (SLOT * (int)sizeof(T))) < 2 ? 2 : (32768 / (SLOT * (int)sizeof(T)));
+    // 32 KB of staged X for k <= 8 (four workgroups per CU), 64 KB for wider blocks
+    static constexpr int LDS_BYTES = LOBPCG_TW_LDS ? LOBPCG_TW_LDS : (KP * (int)sizeof(T) > 32 ? 65536 : 32768);
+    static constexpr int WT0 = LDS_BYTES / NBUF / (SLOT * (int)sizeof(T));
+    static constexpr int WT = WT0 < 2 ? 2 : WT0;       // slots per window
+    static constexpr int VEC = 16 / (int)sizeof(T);    // elements per 16-byte load
+    static constexpr int MAXV = (WT * 64 * KP / VEC + TW_THREADS - 1) / TW_THREADS;  // 16-byte loads per thread
 };
+
+// one 16-byte unit of a staged window (vector path, k == KP): slot s, block row rr, column q
+template <typename T, int KP>
+__device__ inline void tw_unit(int idx, int &s, int &rr, int &q) {
+    constexpr int VEC = TwShape<T, KP>::VEC;
+    constexpr int UPR = KP / VEC;        // 16-byte units per row (power of two)
+    constexpr int PER = 64 * UPR;        // units per 64-row block
+    s = idx / PER;
+    const int rem = idx - s * PER;
+    rr = rem / UPR;
+    q = (rem - rr * UPR) * VEC;
+}
 
 template <typename T, int KP>
 __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
@@ -181,17 +205,51 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
     const int32_t *__restrict__ clist_off, const int32_t *__restrict__ clist,
     const T *__restrict__ diag, const T *__restrict__ X, T *__restrict__ Y) {
     using S = TwShape<T, KP>;
-    constexpr int VEC = 16 / (int)sizeof(T);           // elements per 16-byte load
+    constexpr int VEC = S::VEC;
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
     __shared__ int32_t s_list[TILE_SLOTS];
-    __shared__ __align__(16) T Xs[S::WT * S::SLOT];
+    __shared__ __align__(16) T Xs[NBUF * S::WT * S::SLOT];
     const int64_t I = blockIdx.x;
     const int r = threadIdx.x / GROUP, sl = threadIdx.x % GROUP;
     const int64_t i = I * 64 + r;
     const bool valid = i < n;
-    const bool vec = (k % VEC) == 0;
+    const bool vec = (k % VEC) == 0 && k == KP;
     T acc[KP];
 #pragma unroll
     for (int q = 0; q < KP; ++q) acc[q] = T(0);
+    // stage window [s0, s1) into buffer b (scalar path for k not a multiple of the vector width)
+    auto stage_scalar = [&](int s0, int s1, int b) {
+        const int per = 64 * k;
+        for (int idx = threadIdx.x; idx < (s1 - s0) * per; idx += TW_THREADS) {
+            const int s = idx / per, rem = idx - s * per, rr = rem / k, q = rem - rr * k;
+            const int64_t grow = (int64_t)s_list[s0 + s] * 64 + rr;
+            Xs[(b * S::WT + s) * S::SLOT + rr * S::STRIDE + q] = grow < n ? X[grow * k + q] : T(0);
+        }
+    };
+    V pre[S::MAXV];
+    auto fetch = [&](int s0, int s1) {   // global loads of a window into registers
+#pragma unroll
+        for (int u = 0; u < S::MAXV; ++u) {
+            const int idx = threadIdx.x + u * TW_THREADS;
+            if (idx < (s1 - s0) * (64 * KP / VEC)) {
+                int s, rr, q;
+                tw_unit<T, KP>(idx, s, rr, q);
+                const int64_t grow = (int64_t)s_list[s0 + s] * 64 + rr;
+                pre[u] = grow < n ? *reinterpret_cast<const V *>(X + grow * KP + q) : V{};
+            }
+        }
+    };
+    auto deposit = [&](int s0, int s1, int b) {   // registers into LDS buffer b
+#pragma unroll
+        for (int u = 0; u < S::MAXV; ++u) {
+            const int idx = threadIdx.x + u * TW_THREADS;
+            if (idx < (s1 - s0) * (64 * KP / VEC)) {
+                int s, rr, q;
+                tw_unit<T, KP>(idx, s, rr, q);
+                *reinterpret_cast<V *>(&Xs[(b * S::WT + s) * S::SLOT + rr * S::STRIDE + q]) = pre[u];
+            }
+        }
+    };
     for (int view = 0; view < 2; ++view) {
         const int32_t *loff = view == 0 ? rlist_off : clist_off;
         const int32_t *list = view == 0 ? rlist : clist;
@@ -201,60 +259,79 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
         const int l0 = loff[I], nslots = loff[I + 1] - l0;
         __syncthreads();  // the previous view is done with s_list and Xs
         for (int t = threadIdx.x; t < nslots; t += TW_THREADS) s_list[t] = list[l0 + t];
-        int64_t e = 0, e_end = 0;
+        // this lane's chunks of its row segment: chunk m (8 entries) belongs to lane m % 8
+        int64_t pos = 0, seg_end = 0;
+        int off = 0;   // entries of the current chunk already consumed
         if (valid) {
-            e = ptr[i] + sl;
-            e_end = ptr[i + 1];
+            pos = ptr[i] + 8 * sl;
+            seg_end = ptr[i + 1];
         }
-        for (int s0 = 0; s0 < nslots; s0 += S::WT) {
-            const int s1 = min(s0 + S::WT, nslots);
-            __syncthreads();  // s_list visible; the previous window is consumed
+        __syncthreads();
+        if (nslots > 0) {
             if (vec) {
-                const int per = 64 * k / VEC;   // 16-byte units per block
-                for (int idx = threadIdx.x; idx < (s1 - s0) * per; idx += TW_THREADS) {
-                    const int s = idx / per, rem = idx - s * per;
-                    const int rr = rem / (k / VEC), q = (rem - rr * (k / VEC)) * VEC;
-                    const int64_t grow = (int64_t)s_list[s0 + s] * 64 + rr;
-                    T *dst = &Xs[s * S::SLOT + rr * S::STRIDE + q];
-                    if constexpr (sizeof(T) == 4) {
-                        float4 val = grow < n ? *reinterpret_cast<const float4 *>(X + grow * k + q) : float4{0, 0, 0, 0};
-                        *reinterpret_cast<float4 *>(dst) = val;
-                    } else {
-                        double2 val = grow < n ? *reinterpret_cast<const double2 *>(X + grow * k + q) : double2{0, 0};
-                        *reinterpret_cast<double2 *>(dst) = val;
+                fetch(0, min(S::WT, nslots));
+                deposit(0, min(S::WT, nslots), 0);
+            } else {
+                stage_scalar(0, min(S::WT, nslots), 0);
+            }
+        }
+        int w = 0;
+        for (int s0 = 0; s0 < nslots; s0 += S::WT, ++w) {
+            const int s1 = min(s0 + S::WT, nslots);
+            const int b = NBUF == 2 ? (w & 1) : 0;
+            const int n0 = s1, n1 = min(s1 + S::WT, nslots);
+            __syncthreads();  // buffer b holds window [s0, s1)
+            if (NBUF == 2 && vec && n0 < n1) fetch(n0, n1);   // next window in flight during this one
+            bool more = pos < seg_end;
+            while (more) {
+                const uint4 uu = *reinterpret_cast<const uint4 *>(ix + pos);
+                unsigned u[8] = {uu.x & 0xFFFFu, uu.x >> 16, uu.y & 0xFFFFu, uu.y >> 16,
+                                 uu.z & 0xFFFFu, uu.z >> 16, uu.w & 0xFFFFu, uu.w >> 16};
+                T v[8];
+                if constexpr (sizeof(T) == 4) {
+                    const float4 a = *reinterpret_cast<const float4 *>(vals + pos);
+                    const float4 c = *reinterpret_cast<const float4 *>(vals + pos + 4);
+                    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                    v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const double2 a = *reinterpret_cast<const double2 *>(vals + pos + 2 * h);
+                        v[2 * h] = a.x;
+                        v[2 * h + 1] = a.y;
                     }
                 }
-            } else {
-                const int per = 64 * k;
-                for (int idx = threadIdx.x; idx < (s1 - s0) * per; idx += TW_THREADS) {
-                    const int s = idx / per, rem = idx - s * per, rr = rem / k, q = rem - rr * k;
-                    const int64_t grow = (int64_t)s_list[s0 + s] * 64 + rr;
-                    Xs[s * S::SLOT + rr * S::STRIDE + q] = grow < n ? X[grow * k + q] : T(0);
+                // the code slot*64 + c is the staged row index; rows of this window
+                // start at s0*64, and padding (0xFFFF) never falls below lim
+                const unsigned lim = (unsigned)s1 * 64u, base = (unsigned)s0 * 64u;
+                const T *xb = &Xs[b * S::WT * S::SLOT];
+                int nb = 0;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) nb += u[t] < lim ? 1 : 0;
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (t >= off && t < nb) axpy_row<T, KP>(acc, v[t], xb + (u[t] - base) * S::STRIDE, k);
+                off = nb;   // slots are sorted within the chunk: [old off, nb) was just consumed
+                if (off == 8) {
+                    pos += 8 * GROUP;
+                    off = 0;
+                    more = pos < seg_end;
+                } else {
+                    more = false;
                 }
             }
-            __syncthreads();
-            bool more = e < e_end;
-            while (more) {
-                unsigned u[BATCH];
-                T v[BATCH];
-#pragma unroll
-                for (int t = 0; t < BATCH; ++t) {
-                    const int64_t ee = e + (int64_t)t * GROUP;
-                    const bool ok = ee < e_end;
-                    u[t] = ok ? (unsigned)ix[ee] : 0xFFFFu;   // slot 1023: never inside a window
-                    v[t] = ok ? vals[ee] : T(0);
-                }
-                int consumed = 0;
-#pragma unroll
-                for (int t = 0; t < BATCH; ++t) {
-                    const int slot = (int)(u[t] >> 6);
-                    if (slot < s1) {
-                        axpy_row<T, KP>(acc, v[t], &Xs[(slot - s0) * S::SLOT + (u[t] & 63) * S::STRIDE], k);
-                        ++consumed;
+            if (n0 < n1) {
+                if (NBUF == 2 && vec) {
+                    deposit(n0, n1, b ^ 1);   // the other buffer was last read before the barrier above
+                } else {
+                    __syncthreads();          // single buffer: everyone is done reading window [s0, s1)
+                    if (vec) {
+                        fetch(n0, n1);
+                        deposit(n0, n1, 0);
+                    } else {
+                        stage_scalar(n0, n1, NBUF == 2 ? (b ^ 1) : 0);
                     }
                 }
-                e += (int64_t)consumed * GROUP;
-                more = consumed == BATCH && e < e_end;
             }
         }
     }
@@ -433,17 +510,56 @@ int build_csc(lobpcg_ctx *ctx, hipStream_t s) {
         rflat.insert(rflat.end(), rl[I].begin(), rl[I].end());
         cflat.insert(cflat.end(), cl[I].begin(), cl[I].end());
     }
+    // pad every row segment of both views to a multiple of 8 entries (index
+    // 0xFFFF = slot 1023, never inside a window; value 0) so that each lane
+    // reads whole 8-entry chunks with 16-byte loads
+    auto pad8 = [&](const std::vector<int64_t> &ptr, const std::vector<uint16_t> &ix, const std::vector<T> &vv,
+                    std::vector<int64_t> &ptr8, std::vector<uint16_t> &ix8, std::vector<T> &v8) {
+        ptr8.assign(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) ptr8[i + 1] = ptr8[i] + ((ptr[i + 1] - ptr[i] + 7) / 8) * 8;
+        ix8.assign(ptr8[n], (uint16_t)0xFFFF);
+        v8.assign(ptr8[n], T(0));
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+                ix8[ptr8[i] + (e - ptr[i])] = ix[e];
+                v8[ptr8[i] + (e - ptr[i])] = vv[e];
+            }
+    };
+    std::vector<int64_t> rp8, cp8;
+    std::vector<uint16_t> rix8, cix8;
+    std::vector<T> rv8, cv8;
+    {
+        std::thread t1([&]() { pad8(rp, rix, val, rp8, rix8, rv8); });
+        pad8(cp, cix, cv, cp8, cix8, cv8);
+        t1.join();
+    }
+    const int64_t mr = rp8[n], mc = cp8[n];
+    // the padded views replace the 32-bit-index arrays on the device
+    (void)hipFree(ctx->ci);
+    (void)hipFree(ctx->cri);
+    (void)hipFree(ctx->val);
+    (void)hipFree(ctx->cval);
+    ctx->ci = nullptr;
+    ctx->cri = nullptr;
+    ctx->val = nullptr;
+    ctx->cval = nullptr;
+    HIP_TRY(ctx, hipMalloc(&ctx->val, std::max<int64_t>(1, mr) * sizeof(T)));
+    HIP_TRY(ctx, hipMalloc(&ctx->cval, std::max<int64_t>(1, mc) * sizeof(T)));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->rp, rp8.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->cp, cp8.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (mr) HIP_TRY(ctx, hipMemcpyAsync(ctx->val, rv8.data(), mr * sizeof(T), hipMemcpyHostToDevice, s));
+    if (mc) HIP_TRY(ctx, hipMemcpyAsync(ctx->cval, cv8.data(), mc * sizeof(T), hipMemcpyHostToDevice, s));
     TiledFormat &tf = ctx->tiled;
-    HIP_TRY(ctx, hipMalloc((void **)&tf.rix, (m ? m : 1) * sizeof(uint16_t)));
-    HIP_TRY(ctx, hipMalloc((void **)&tf.cix, (m ? m : 1) * sizeof(uint16_t)));
+    tf.nent_row = mr;
+    tf.nent_col = mc;
+    HIP_TRY(ctx, hipMalloc((void **)&tf.rix, std::max<int64_t>(1, mr) * sizeof(uint16_t)));
+    HIP_TRY(ctx, hipMalloc((void **)&tf.cix, std::max<int64_t>(1, mc) * sizeof(uint16_t)));
     HIP_TRY(ctx, hipMalloc((void **)&tf.rlist_off, (NT + 1) * sizeof(int32_t)));
     HIP_TRY(ctx, hipMalloc((void **)&tf.clist_off, (NT + 1) * sizeof(int32_t)));
     HIP_TRY(ctx, hipMalloc((void **)&tf.rlist, std::max<size_t>(1, rflat.size()) * sizeof(int32_t)));
     HIP_TRY(ctx, hipMalloc((void **)&tf.clist, std::max<size_t>(1, cflat.size()) * sizeof(int32_t)));
-    if (m) {
-        HIP_TRY(ctx, hipMemcpyAsync(tf.rix, rix.data(), m * sizeof(uint16_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(ctx, hipMemcpyAsync(tf.cix, cix.data(), m * sizeof(uint16_t), hipMemcpyHostToDevice, s));
-    }
+    if (mr) HIP_TRY(ctx, hipMemcpyAsync(tf.rix, rix8.data(), mr * sizeof(uint16_t), hipMemcpyHostToDevice, s));
+    if (mc) HIP_TRY(ctx, hipMemcpyAsync(tf.cix, cix8.data(), mc * sizeof(uint16_t), hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemcpyAsync(tf.rlist_off, roff.data(), (NT + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemcpyAsync(tf.clist_off, coff.data(), (NT + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!rflat.empty())
@@ -454,11 +570,6 @@ int build_csc(lobpcg_ctx *ctx, hipStream_t s) {
     tf.ntilerows = NT;
     tf.nslots_row = (int64_t)rflat.size();
     tf.nslots_col = (int64_t)cflat.size();
-    // the 32-bit index arrays are not needed by the tiled kernels
-    (void)hipFree(ctx->ci);
-    (void)hipFree(ctx->cri);
-    ctx->ci = nullptr;
-    ctx->cri = nullptr;
     ctx->format = LOBPCG_FORMAT_TILED;
     return LOBPCG_OK;
 }
