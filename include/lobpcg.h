@@ -89,6 +89,8 @@ typedef struct {
     /* optional per-phase device time in seconds (filled when timing != 0)      */
     int timing;
     double t_spmm, t_precond_update, t_gram, t_rr, t_orth, t_total;
+    /* optional training-sample harvest (struct lobpcg_harvest below), NULL = off */
+    struct lobpcg_harvest_s *harvest;
 } lobpcg_info;
 
 /* Fill *o with the defaults: F32, GRAM_AUTO, FORMAT_AUTO, tile 64, kmax 16,
@@ -171,6 +173,120 @@ int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B, int kb, d
  */
 int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *X, double *evals, double *rel, double tol,
                  int maxiter, int precond, lobpcg_info *info, void *stream);
+
+/* ======================================================================
+ * Learned preconditioner.
+ *
+ * The paper's preconditioner (Section 3.4) is a shifted diagonal solve; its
+ * 1 x 1-tile form is W_ij = R_ij / s(d_i - theta_j).  The learned variant keeps
+ * that form and multiplies it by exp(o_ij), where o_ij is the output of a
+ * 4 -> 64 -> 64 -> 1 ReLU network of the standardised per-entry features
+ *     f_ij = (d_i, theta_j, rho_i, t_i),  z = (f - mu) / sigma,
+ * rho_i = sum_{j != i} |h_ij| over the full symmetric row and t_i the mean |h|
+ * over the off-diagonal nonzeros of the 64-row tile holding row i.  A network
+ * with zero output reproduces the diagonal preconditioner; any entry whose
+ * scale is not finite falls back to the diagonal one.
+ *
+ * Arithmetic: W1, W2, w3 are used rounded to BF16 (round to nearest even);
+ * the first hidden layer's activations are rounded to BF16 before the second
+ * layer, which runs on BF16 matrix cores with FP32 accumulation; everything
+ * else is FP32.  Training keeps FP32 master weights (Adam).
+ *
+ * Parameter blob (host float[LOBPCG_MLP_NBLOB]), row-major blocks in order:
+ *   W1[64][4], b1[64], W2[64][64] (W2[v][u]: hidden-1 unit u -> hidden-2
+ *   unit v), b2[64], w3[64], b3, mu[4], sigma[4].
+ * Gradients use the first LOBPCG_MLP_NPARAM entries of the same layout.
+ * ====================================================================== */
+#define LOBPCG_MLP_NIN    4
+#define LOBPCG_MLP_HID    64
+#define LOBPCG_MLP_NPARAM 4545   /* trainable: 256 + 64 + 4096 + 64 + 64 + 1   */
+#define LOBPCG_MLP_NBLOB  4553   /* + mu[4] + sigma[4]                          */
+
+/* Create a network on the current device from a host parameter blob (sigma
+ * entries must be > 0).  Adam state starts at zero. */
+int lobpcg_mlp_create(lobpcg_mlp **out, const float *blob);
+void lobpcg_mlp_destroy(lobpcg_mlp *m);
+int lobpcg_mlp_set_params(lobpcg_mlp *m, const float *blob);  /* also resets Adam */
+int lobpcg_mlp_get_params(lobpcg_mlp *m, float *blob);        /* host out        */
+const char *lobpcg_mlp_last_error(const lobpcg_mlp *m);
+
+/* Attach m to ctx for LOBPCG_PRECOND_MLP (NULL detaches).  The context does
+ * not own the network; it must outlive its use by the context. */
+int lobpcg_set_mlp(lobpcg_ctx *ctx, lobpcg_mlp *m);
+
+/* Per-row feature columns of ctx (device float[n] each, NULL to skip): the
+ * full-row off-diagonal 1-norm rho and the tile mean |h| t. */
+int lobpcg_get_features(lobpcg_ctx *ctx, float *rownorm, float *tilemean, void *stream);
+
+/* o[s] = network output for raw features feat[s][0..3] (device float N x 4 in,
+ * device float N out), on the same matrix-core kernel the preconditioner
+ * uses.  N >= 0. */
+int lobpcg_mlp_forward(lobpcg_mlp *m, const float *feat, int64_t N, float *o, void *stream);
+
+/* Set mu, sigma to the mean and standard deviation (sigma floored at 1e-12)
+ * of N >= 2 raw feature rows (device float N x 4). */
+int lobpcg_mlp_fit_standardizer(lobpcg_mlp *m, const float *feat, int64_t N, void *stream);
+
+/* A training batch: samples grouped by (run, iteration, column j); the rows
+ * of one group are contiguous.  Per sample s of group g:
+ *   feat  raw features (d_i, theta_j, rho_i, t_i)
+ *   U     the diagonal step R_ij / s(d_i - theta_j)
+ *   T     the exact correction of column j at row i (its error outside span X)
+ *   w     importance weight of the sampled row
+ *   Xrow  row i of the block X (k values)
+ * Loss of a group, u = exp(o) U, a = sum w Xrow u, u' = u - Xrow . a:
+ *   L_g = 1 - (sum w u' T)^2 / ((sum w u'^2)(sum w T^2)),
+ * 0 (with zero gradient) when either sum of squares is 0; the batch loss is
+ * the mean over groups.  All arrays are device memory owned by the caller. */
+typedef struct {
+    int64_t nsamples;
+    int ngroups;
+    int k;                       /* 1..16 */
+    const float *feat;           /* nsamples x 4 */
+    const float *U, *T, *w;      /* nsamples each */
+    const float *Xrow;           /* nsamples x k */
+    const int64_t *group_off;    /* ngroups + 1, group_off[0] = 0, nondecreasing */
+} lobpcg_mlp_batch;
+
+/* Loss and its gradient (host double *loss, host float grad[NPARAM], either
+ * may be NULL) at the current parameters; synchronous. */
+int lobpcg_mlp_loss_grad(lobpcg_mlp *m, const lobpcg_mlp_batch *b, double *loss, float *grad, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch's gradient;
+ * *loss (host, may be NULL) receives the loss before the step.  Synchronous. */
+int lobpcg_mlp_train_step(lobpcg_mlp *m, const lobpcg_mlp_batch *b, float lr, double *loss, void *stream);
+
+/* Harvest of training samples from a running solve (set info->harvest).
+ * At every iteration it with it % every == 0, for each column j < nev, the
+ * exact correction E_j = x*_j - X (X^T x*_j) is formed from converged
+ * eigenvectors x* of the same matrix, and row i is kept with probability
+ *   p_i = min(1, rows (1/(2n) + |E_ij| / (2 sum_l |E_lj|)))
+ * (uniform draw: SplitMix64 of (seed, group, i), see the implementation),
+ * weight w = 1/p_i.  Each (iteration, column) becomes one group appended to
+ * the output arrays.  When the next group might not fit (capacity below
+ * nsamples + n or groups exhausted) harvesting stops and `full` is set. */
+typedef struct lobpcg_harvest_s {
+    int every;                   /* >= 1 */
+    int rows;                    /* >= 1, expected rows per group */
+    int nev;                     /* columns harvested, 1..k */
+    const void *xstar;           /* device, n x nev row-major, context dtype */
+    uint64_t seed;
+    int64_t capacity;            /* samples the arrays below hold */
+    int capacity_groups;
+    float *feat, *U, *T, *w;     /* device outputs (capacity x 4, capacity, ...) */
+    float *Xrow;                 /* device, capacity x k */
+    int32_t *row;                /* device, capacity, row index i (NULL to skip) */
+    int64_t *group_off;          /* device, capacity_groups + 1 */
+    int64_t nsamples;            /* in: samples already held; out: total */
+    int ngroups;                 /* in: groups already held; out: total */
+    int full;                    /* out */
+} lobpcg_harvest;
+
+/* One harvest step on a caller-supplied block: X, HX device n x k (context
+ * dtype), theta device double[k]; appends h->nev groups to *h (as the solve
+ * does every h->every iterations).  Synchronous. */
+int lobpcg_harvest_block(lobpcg_ctx *ctx, const void *X, const void *HX, const double *theta, int k,
+                         lobpcg_harvest *h, void *stream);
 
 /* Matrix facts computed at create: n, stored nnz (incl. diagonal), format in
  * use, dtype, and the Gershgorin bound gamma.  Any output pointer may be NULL. */

@@ -49,6 +49,25 @@ struct TiledFormat {
     int32_t *clist = nullptr;      // tile-row index per column-view slot
 };
 
+// Learned preconditioner: FP32 master parameters (the host blob layout) and
+// training state, all on the device the network was created on.
+struct lobpcg_mlp {
+    int device = 0;
+    float *params = nullptr;        // LOBPCG_MLP_NBLOB
+    float *adam_m = nullptr, *adam_v = nullptr;  // LOBPCG_MLP_NPARAM each
+    int adam_t = 0;
+    float *grad = nullptr;          // LOBPCG_MLP_NPARAM
+    float *grad_partial = nullptr;  // [grad_max_parts][LOBPCG_MLP_NPARAM]
+    int grad_max_parts = 0;
+    float *so = nullptr;            // per-sample network output, then dL/do
+    int64_t so_cap = 0;
+    double *gloss = nullptr;        // per-group loss
+    int gloss_cap = 0;
+    double *loss = nullptr;         // 1
+    std::string err;
+};
+int set_mlp_err(lobpcg_mlp *m, int code, const char *fmt, ...);
+
 struct lobpcg_ctx {
     int64_t n = 0, nnz = 0, nnz_off = 0;
     int dtype = LOBPCG_F32, format = LOBPCG_FORMAT_CSR, format_request = LOBPCG_FORMAT_AUTO, tile = 64, kmax = 16, gram = LOBPCG_GRAM_AUTO;
@@ -85,6 +104,7 @@ struct lobpcg_ctx {
     Report *report_host = nullptr;   // pinned
     int *dflags = nullptr;
     lobpcg_mlp *mlp = nullptr;
+    unsigned long long *harvest_counter = nullptr;
     hipEvent_t ev[8] = {};
     std::string err;
 };
@@ -125,3 +145,6 @@ int launch_rayleigh_quotients(lobpcg_ctx *ctx, int k, hipStream_t s);
 int launch_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, int kind,
                    hipStream_t s);
 int mlp_precond_ready(lobpcg_ctx *ctx);
+int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s);
+// one harvest snapshot after iteration `it` of a solve (X, HX, rr_theta current)
+int harvest_snapshot(lobpcg_ctx *ctx, int k, lobpcg_harvest *h, hipStream_t s);

@@ -19,7 +19,6 @@
 #include "internal.hpp"
 
 int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s);
-int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s);
 
 namespace {
 
@@ -226,6 +225,10 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             tm.mark(2);
             TRY(read_report(ctx, s));
             t_spmm += tm.span(0, 1); t_upd += tm.span(1, 2);
+        }
+        if (info && info->harvest && it % std::max(1, info->harvest->every) == 0 && !info->harvest->full) {
+            // training samples for the learned preconditioner from this iterate
+            TRY(harvest_snapshot(ctx, k, info->harvest, s));
         }
         if (trace_every && it % trace_every == 0) {
             rel_from_report(ctx, k, tau, rel.data(), &finite);

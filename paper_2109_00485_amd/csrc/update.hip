@@ -8,7 +8,6 @@
 // coefficient matrices are staged once per workgroup in LDS.
 #include "internal.hpp"
 
-int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s);
 
 namespace {
 
