@@ -23,7 +23,8 @@ with importance weights w_i (the rows are a sample of the column):
     L_g  = 1 - (sum w u' T)^2 / ((sum w u'^2)(sum w T^2))
 with T the exact correction of the column (its error outside span(X)).  L_g is
 invariant to the scale of the direction, which the Rayleigh-Ritz step does not
-see either; the loss is the mean over groups.  Parity of what the trained
+see either; the loss is the mean over groups.  A group with sum w u'^2 = 0 or
+sum w T^2 = 0 has no defined angle and contributes 0 with zero gradient.  Parity of what the trained
 network gains is unpinned: it is judged by iteration counts, not by a
 reference.
 """
@@ -77,12 +78,20 @@ def standardize(p: Params, f: np.ndarray) -> np.ndarray:
     return (np.asarray(f, dtype=np.float64) - p.mu) / p.sigma
 
 
-def forward(p: Params, z: np.ndarray, bf16: bool = True):
+def forward(p: Params, z: np.ndarray, bf16: bool = True, a1_f32: bool = False):
     """o = w3 . relu(W2 bf16(relu(W1 z + b1)) + b2) + b3 with BF16 weights
-    (``bf16=False`` evaluates the same network without the roundings)."""
+    (``bf16=False`` evaluates the same network without the roundings).
+
+    ``a1_f32``: form the first layer's pre-activations in FP32 (inputs, weights
+    and sum rounded to FP32), the precision in which the kernels take the BF16
+    rounding decision of the hidden activations; everything else stays FP64."""
     rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     W1, W2, w3 = rnd(p.W1), rnd(p.W2), rnd(p.w3)
-    a1 = z @ W1.T + p.b1
+    if a1_f32:
+        z32 = np.asarray(z, dtype=np.float32)
+        a1 = (z32 @ W1.T.astype(np.float32) + np.asarray(p.b1, dtype=np.float32)).astype(np.float64)
+    else:
+        a1 = z @ W1.T + p.b1
     h1 = np.maximum(a1, 0.0)
     h1b = rnd(h1)
     a2 = h1b @ W2.T + p.b2
@@ -96,7 +105,7 @@ def guard(x, eps):
     return np.where(np.abs(x) >= eps, x, np.where(x < 0, -eps, eps))
 
 
-def precond_scale(p: Params, d, theta, rownorm, tilemean, eps) -> np.ndarray:
+def precond_scale(p: Params, d, theta, rownorm, tilemean, eps, a1_f32: bool = False) -> np.ndarray:
     """m_ij (n x k) for every row i and Ritz value theta_j; non-finite -> diagonal."""
     d = np.asarray(d, dtype=np.float64)
     theta = np.asarray(theta, dtype=np.float64)
@@ -106,20 +115,20 @@ def precond_scale(p: Params, d, theta, rownorm, tilemean, eps) -> np.ndarray:
     f[:, :, 1] = theta[None, :]
     f[:, :, 2] = np.asarray(rownorm, dtype=np.float64)[:, None]
     f[:, :, 3] = np.asarray(tilemean, dtype=np.float64)[:, None]
-    o, _ = forward(p, standardize(p, f.reshape(-1, NIN)))
+    o, _ = forward(p, standardize(p, f.reshape(-1, NIN)), a1_f32=a1_f32)
     o = o.reshape(n, k)
     base = 1.0 / guard(d[:, None] - theta[None, :], eps)
     m = np.exp(o) * base
     return np.where(np.isfinite(m), m, base)
 
 
-def group_loss(p: Params, feat, U, T, w, X, gid, ngroups, with_grad=True, bf16=True):
+def group_loss(p: Params, feat, U, T, w, X, gid, ngroups, with_grad=True, bf16=True, a1_f32=False):
     """Mean group loss and (optionally) the gradients w.r.t. W1, b1, W2, b2, w3, b3.
 
     feat: N x 4 raw features; U, T, w: N; X: N x k (row i of the block X); gid: N ints.
     """
     z = standardize(p, feat)
-    o, (z, a1, h1b, a2, h2, W1b, W2b, w3b) = forward(p, z, bf16=bf16)
+    o, (z, a1, h1b, a2, h2, W1b, W2b, w3b) = forward(p, z, bf16=bf16, a1_f32=a1_f32)
     e = np.exp(o)
     u = e * U
     k = X.shape[1]
@@ -129,13 +138,17 @@ def group_loss(p: Params, feat, U, T, w, X, gid, ngroups, with_grad=True, bf16=T
     S_uT = np.bincount(gid, w * up * T, ngroups)
     S_uu = np.bincount(gid, w * up * up, ngroups)
     S_TT = np.bincount(gid, w * T * T, ngroups)
-    Lg = 1.0 - S_uT ** 2 / (S_uu * S_TT)
+    # a group whose direction or target vanishes has no defined angle: loss 0, no gradient
+    valid = (S_uu > 0) & (S_TT > 0)
+    den = np.where(valid, S_uu * S_TT, 1.0)
+    Lg = np.where(valid, 1.0 - S_uT ** 2 / den, 0.0)
     L = float(Lg.mean())
     if not with_grad:
         return L, None
     # dL/du'_i for the mean over groups
     coef = 1.0 / ngroups
-    g_up = -2.0 * w * (S_uT[gid] * T * S_uu[gid] - S_uT[gid] ** 2 * up) / (S_uu[gid] ** 2 * S_TT[gid]) * coef
+    den2 = np.where(valid, S_uu ** 2 * S_TT, 1.0)
+    g_up = np.where(valid[gid], -2.0 * w * (S_uT[gid] * T * S_uu[gid] - S_uT[gid] ** 2 * up) / den2[gid] * coef, 0.0)
     Gx = np.zeros((ngroups, k))
     np.add.at(Gx, gid, g_up[:, None] * X)
     g_u = g_up - w * np.einsum("ij,ij->i", X, Gx[gid])

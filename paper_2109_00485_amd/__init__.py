@@ -44,7 +44,29 @@ class Info(ctypes.Structure):
                 ("theta_hist", ctypes.POINTER(ctypes.c_double)), ("rel_hist", ctypes.POINTER(ctypes.c_double)),
                 ("timing", ctypes.c_int),
                 ("t_spmm", ctypes.c_double), ("t_precond_update", ctypes.c_double), ("t_gram", ctypes.c_double),
-                ("t_rr", ctypes.c_double), ("t_orth", ctypes.c_double), ("t_total", ctypes.c_double)]
+                ("t_rr", ctypes.c_double), ("t_orth", ctypes.c_double), ("t_total", ctypes.c_double),
+                ("harvest", ctypes.c_void_p)]
+
+
+MLP_NIN, MLP_HID, MLP_NPARAM, MLP_NBLOB = 4, 64, 4545, 4553
+# blob layout: (name, shape) in order
+MLP_LAYOUT = (("W1", (64, 4)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("w3", (64,)), ("b3", ()),
+              ("mu", (4,)), ("sigma", (4,)))
+
+
+class Harvest(ctypes.Structure):
+    _fields_ = [("every", ctypes.c_int), ("rows", ctypes.c_int), ("nev", ctypes.c_int),
+                ("xstar", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("capacity", ctypes.c_int64),
+                ("capacity_groups", ctypes.c_int), ("feat", ctypes.c_void_p), ("U", ctypes.c_void_p),
+                ("T", ctypes.c_void_p), ("w", ctypes.c_void_p), ("Xrow", ctypes.c_void_p),
+                ("row", ctypes.c_void_p), ("group_off", ctypes.c_void_p), ("nsamples", ctypes.c_int64),
+                ("ngroups", ctypes.c_int), ("full", ctypes.c_int)]
+
+
+class MlpBatch(ctypes.Structure):
+    _fields_ = [("nsamples", ctypes.c_int64), ("ngroups", ctypes.c_int), ("k", ctypes.c_int),
+                ("feat", ctypes.c_void_p), ("U", ctypes.c_void_p), ("T", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("Xrow", ctypes.c_void_p), ("group_off", ctypes.c_void_p)]
 
 
 _lib = None
@@ -83,6 +105,31 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_strerror.argtypes = [cint]
     lib.lobpcg_last_error.restype = ctypes.c_char_p
     lib.lobpcg_last_error.argtypes = [P]
+    fptr = ctypes.POINTER(ctypes.c_float)
+    lib.lobpcg_mlp_create.restype = cint
+    lib.lobpcg_mlp_create.argtypes = [ctypes.POINTER(P), fptr]
+    lib.lobpcg_mlp_destroy.restype = None
+    lib.lobpcg_mlp_destroy.argtypes = [P]
+    lib.lobpcg_mlp_set_params.restype = cint
+    lib.lobpcg_mlp_set_params.argtypes = [P, fptr]
+    lib.lobpcg_mlp_get_params.restype = cint
+    lib.lobpcg_mlp_get_params.argtypes = [P, fptr]
+    lib.lobpcg_mlp_last_error.restype = ctypes.c_char_p
+    lib.lobpcg_mlp_last_error.argtypes = [P]
+    lib.lobpcg_set_mlp.restype = cint
+    lib.lobpcg_set_mlp.argtypes = [P, P]
+    lib.lobpcg_get_features.restype = cint
+    lib.lobpcg_get_features.argtypes = [P, P, P, P]
+    lib.lobpcg_mlp_forward.restype = cint
+    lib.lobpcg_mlp_forward.argtypes = [P, P, i64, P, P]
+    lib.lobpcg_mlp_fit_standardizer.restype = cint
+    lib.lobpcg_mlp_fit_standardizer.argtypes = [P, P, i64, P]
+    lib.lobpcg_mlp_loss_grad.restype = cint
+    lib.lobpcg_mlp_loss_grad.argtypes = [P, ctypes.POINTER(MlpBatch), ctypes.POINTER(dbl), fptr, P]
+    lib.lobpcg_mlp_train_step.restype = cint
+    lib.lobpcg_mlp_train_step.argtypes = [P, ctypes.POINTER(MlpBatch), ctypes.c_float, ctypes.POINTER(dbl), P]
+    lib.lobpcg_harvest_block.restype = cint
+    lib.lobpcg_harvest_block.argtypes = [P, P, P, P, cint, ctypes.POINTER(Harvest), P]
     _lib = lib
     return lib
 
@@ -224,8 +271,30 @@ class Context:
                                        _dev_ptr(G, torch.float64, "G"), prec, _stream_ptr(stream)), "gram")
         return G
 
+    def set_mlp(self, mlp):
+        """Attach a network for PRECOND_MLP (None detaches); keep it alive while attached."""
+        self._mlp = mlp
+        self._check(load().lobpcg_set_mlp(self._h, mlp._h if mlp is not None else None), "set_mlp")
+
+    def features(self, stream=None):
+        """(rownorm, tilemean): the per-row network inputs, device float32[n] each."""
+        import torch
+        r = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        t = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        self._check(load().lobpcg_get_features(self._h, _dev_ptr(r), _dev_ptr(t), _stream_ptr(stream)), "features")
+        return r, t
+
+    def harvest_block(self, X, HX, theta, hb, stream=None):
+        """One harvest step on (X, H X, theta) into the HarvestBuffer hb."""
+        import torch
+        self._check(load().lobpcg_harvest_block(self._h, _dev_ptr(X, self.torch_dtype, "X"),
+                                                _dev_ptr(HX, self.torch_dtype, "HX"),
+                                                _dev_ptr(theta, torch.float64, "theta"), X.shape[1],
+                                                ctypes.byref(hb.h), _stream_ptr(stream)), "harvest_block")
+        return hb
+
     def solve(self, X, nev, tol=1e-6, maxiter=5000, precond=PRECOND_DIAG, history=False, timing=False,
-              stream=None, raise_on_noconv=False) -> SolveResult:
+              stream=None, raise_on_noconv=False, harvest=None) -> SolveResult:
         k = X.shape[1]
         evals = np.zeros(k)
         rel = np.zeros(k)
@@ -237,6 +306,8 @@ class Context:
             info.theta_hist = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             info.rel_hist = rh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         info.timing = int(bool(timing))
+        if harvest is not None:
+            info.harvest = ctypes.cast(ctypes.pointer(harvest.h), ctypes.c_void_p)
         rc = load().lobpcg_solve(self._h, k, nev, _dev_ptr(X, self.torch_dtype, "X"),
                                  evals.ctypes.data_as(ctypes.c_void_p), rel.ctypes.data_as(ctypes.c_void_p),
                                  float(tol), int(maxiter), int(precond), ctypes.byref(info), _stream_ptr(stream))
@@ -251,3 +322,163 @@ class Context:
             res.theta_hist = th.reshape(-1, k)[:info.iters]
             res.rel_hist = rh.reshape(-1, k)[:info.iters]
         return res
+
+
+# -- learned preconditioner ----------------------------------------------------------------------
+def pack_params(p: dict) -> np.ndarray:
+    """Parameter blob (float32[MLP_NBLOB]) from a dict of arrays named as in MLP_LAYOUT."""
+    parts = [np.asarray(p[name], dtype=np.float32).reshape(shape) for name, shape in MLP_LAYOUT]
+    blob = np.concatenate([x.ravel() for x in parts]).astype(np.float32)
+    assert blob.size == MLP_NBLOB
+    return blob
+
+
+def unpack_params(blob) -> dict:
+    blob = np.asarray(blob, dtype=np.float32)
+    out, o = {}, 0
+    for name, shape in MLP_LAYOUT:
+        size = int(np.prod(shape)) if shape else 1
+        out[name] = blob[o:o + size].reshape(shape).copy() if shape else float(blob[o])
+        o += size
+    return out
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Mlp:
+    """The 4 -> 64 -> 64 -> 1 preconditioner network on the current device."""
+
+    def __init__(self, params):
+        lib = load()
+        blob = np.ascontiguousarray(params if isinstance(params, np.ndarray) else pack_params(params),
+                                    dtype=np.float32)
+        h = ctypes.c_void_p()
+        rc = lib.lobpcg_mlp_create(ctypes.byref(h), _fptr(blob))
+        if rc != OK:
+            raise LobpcgError(rc, "mlp_create: " + lib.lobpcg_strerror(rc).decode())
+        self._h = h
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = load().lobpcg_mlp_last_error(self._h).decode()
+            raise LobpcgError(rc, f"{what}: {msg or load().lobpcg_strerror(rc).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lobpcg_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        blob = np.ascontiguousarray(params if isinstance(params, np.ndarray) else pack_params(params),
+                                    dtype=np.float32)
+        self._check(load().lobpcg_mlp_set_params(self._h, _fptr(blob)), "set_params")
+
+    def params(self) -> np.ndarray:
+        blob = np.zeros(MLP_NBLOB, dtype=np.float32)
+        self._check(load().lobpcg_mlp_get_params(self._h, _fptr(blob)), "get_params")
+        return blob
+
+    def forward(self, feat, out=None, stream=None):
+        import torch
+        N = feat.shape[0]
+        if out is None:
+            out = torch.empty(N, dtype=torch.float32, device=feat.device)
+        self._check(load().lobpcg_mlp_forward(self._h, _dev_ptr(feat, torch.float32, "feat"), N,
+                                              _dev_ptr(out, torch.float32, "o"), _stream_ptr(stream)), "forward")
+        return out
+
+    def fit_standardizer(self, feat, stream=None):
+        import torch
+        self._check(load().lobpcg_mlp_fit_standardizer(self._h, _dev_ptr(feat, torch.float32, "feat"),
+                                                       feat.shape[0], _stream_ptr(stream)), "fit_standardizer")
+
+    def loss_grad(self, batch, stream=None):
+        loss = ctypes.c_double()
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(load().lobpcg_mlp_loss_grad(self._h, ctypes.byref(batch.b), ctypes.byref(loss), _fptr(g),
+                                                _stream_ptr(stream)), "loss_grad")
+        return loss.value, g
+
+    def train_step(self, batch, lr, stream=None):
+        loss = ctypes.c_double()
+        self._check(load().lobpcg_mlp_train_step(self._h, ctypes.byref(batch.b), float(lr), ctypes.byref(loss),
+                                                 _stream_ptr(stream)), "train_step")
+        return loss.value
+
+
+class Batch:
+    """Device training batch (keeps the tensors alive)."""
+
+    def __init__(self, feat, U, T, w, Xrow, group_off):
+        import torch
+        self.t = (feat, U, T, w, Xrow, group_off)
+        b = MlpBatch()
+        b.nsamples = feat.shape[0]
+        b.ngroups = group_off.shape[0] - 1
+        b.k = Xrow.shape[1]
+        b.feat = _dev_ptr(feat, torch.float32, "feat").value
+        b.U = _dev_ptr(U, torch.float32, "U").value
+        b.T = _dev_ptr(T, torch.float32, "T").value
+        b.w = _dev_ptr(w, torch.float32, "w").value
+        b.Xrow = _dev_ptr(Xrow, torch.float32, "Xrow").value
+        b.group_off = _dev_ptr(group_off, torch.int64, "group_off").value
+        self.b = b
+
+
+class HarvestBuffer:
+    """Device arrays a solve (or harvest_block) appends training samples to."""
+
+    def __init__(self, capacity, capacity_groups, k, xstar, nev, every=1, rows=1024, seed=0, rows_index=True):
+        import torch
+        dev = xstar.device
+        self.feat = torch.zeros((capacity, 4), dtype=torch.float32, device=dev)
+        self.U = torch.zeros(capacity, dtype=torch.float32, device=dev)
+        self.T = torch.zeros(capacity, dtype=torch.float32, device=dev)
+        self.w = torch.zeros(capacity, dtype=torch.float32, device=dev)
+        self.Xrow = torch.zeros((capacity, k), dtype=torch.float32, device=dev)
+        self.row = torch.zeros(capacity, dtype=torch.int32, device=dev) if rows_index else None
+        self.group_off = torch.zeros(capacity_groups + 1, dtype=torch.int64, device=dev)
+        self.k = k
+        h = Harvest()
+        h.every, h.rows, h.nev, h.seed = every, rows, nev, seed
+        h.capacity, h.capacity_groups = capacity, capacity_groups
+        h.feat, h.U, h.T, h.w = (self.feat.data_ptr(), self.U.data_ptr(), self.T.data_ptr(), self.w.data_ptr())
+        h.Xrow = self.Xrow.data_ptr()
+        h.row = self.row.data_ptr() if self.row is not None else None
+        h.group_off = self.group_off.data_ptr()
+        self.h = h
+        self.set_xstar(xstar, nev)
+
+    def set_xstar(self, xstar, nev=None, seed=None):
+        if not xstar.is_contiguous():
+            raise ValueError("xstar must be contiguous")
+        self._xstar = xstar
+        self.h.xstar = xstar.data_ptr()
+        if nev is not None:
+            self.h.nev = nev
+        if seed is not None:
+            self.h.seed = seed
+
+    @property
+    def nsamples(self):
+        return int(self.h.nsamples)
+
+    @property
+    def ngroups(self):
+        return int(self.h.ngroups)
+
+    @property
+    def full(self):
+        return bool(self.h.full)
+
+    def batch(self):
+        n, g = self.nsamples, self.ngroups
+        return Batch(self.feat[:n], self.U[:n], self.T[:n], self.w[:n], self.Xrow[:n], self.group_off[:g + 1])

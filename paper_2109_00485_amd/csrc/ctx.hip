@@ -281,7 +281,7 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
               hipMalloc(&ctx->HW, blk) == hipSuccess && hipMalloc(&ctx->HP, blk) == hipSuccess;
     ctx->gram_max_wg = 1024;
     ctx->norm_max_wg = 2048;
-    ok = ok && hipMalloc((void **)&ctx->gram_partial, (size_t)ctx->gram_max_wg * 48 * 96 * sizeof(double)) == hipSuccess &&
+    ok = ok && hipMalloc((void **)&ctx->gram_partial, ((size_t)ctx->gram_max_wg + ctx->gram_max_wg / 64 + 1) * 48 * 96 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->gram_out, 48 * 96 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->gram_out2, 48 * 96 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->rr_C, 48 * 16 * sizeof(double)) == hipSuccess &&

@@ -1,5 +1,5 @@
-// Small dense FP64 steps, each one workgroup of a single wavefront (the
-// matrices are at most 48 x 48, so the work is latency-bound):
+// Small dense FP64 steps, each one workgroup (the matrices are at most
+// 48 x 48, so the work is latency-bound):
 //  * Cholesky factor and triangular inverse for Cholesky QR (Section 3.5):
 //    B = W^T W = R^T R, then R^{-1} is applied to W by the combine kernel;
 //  * Rayleigh-Ritz (eq. rreig): assemble G = S^T H S and O = S^T S from the
@@ -17,7 +17,7 @@ namespace {
 
 constexpr int NMAX = 48;
 constexpr int LD = NMAX + 1;
-constexpr int QMAX = (NMAX * NMAX + LOBPCG_WAVE - 1) / LOBPCG_WAVE;
+constexpr int KM_CHOL = 16;   // Cholesky QR block width bound (kmax)
 
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -25,7 +25,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // In-place lower Cholesky of the N x N matrix a (row-major, leading dim LD).
-// Returns false if a pivot falls below tol.  Single wavefront.
+// Returns false if a pivot falls below tol.  Any workgroup size.
 __device__ bool chol_lower(double *a, int N, double tol) {
     const int t = threadIdx.x;
     __shared__ int bad;
@@ -40,7 +40,7 @@ __device__ bool chol_lower(double *a, int N, double tol) {
         }
         __syncthreads();
         const double piv = a[j * LD + j];
-        for (int i = j + 1 + t; i < N; i += LOBPCG_WAVE) {
+        for (int i = j + 1 + t; i < N; i += blockDim.x) {
             double v = a[i * LD + j];
             for (int p = 0; p < j; ++p) v -= a[i * LD + p] * a[j * LD + p];
             a[i * LD + j] = v / piv;
@@ -90,23 +90,39 @@ __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__rest
     }
     // R' = L^T (upper); Rinv' = R'^{-1} by back substitution per column c,
     // Rinv = diag(sc) Rinv' so that W diag(sc) R'^{-1} has orthonormal columns.
+    __shared__ double y[KM_CHOL * LD];
     if (t < k) {
         const int c = t;
-        double y[NMAX];
         for (int i = k - 1; i >= 0; --i) {
             double v = (i == c) ? 1.0 : 0.0;
-            for (int p = i + 1; p < k; ++p) v -= a[p * LD + i] * y[p];   // R'[i][p] = L[p][i]
-            y[i] = v / a[i * LD + i];
+            for (int p = i + 1; p < k; ++p) v -= a[p * LD + i] * y[p * KM_CHOL + c];   // R'[i][p] = L[p][i]
+            y[i * KM_CHOL + c] = v / a[i * LD + i];
         }
-        for (int i = 0; i < k; ++i) rinv[i * k + c] = sc[i] * y[i];
+        for (int i = 0; i < k; ++i) rinv[i * k + c] = sc[i] * y[i * KM_CHOL + c];
     }
 }
 
 // Rayleigh-Ritz.  M is the Gram output [X W P]^T [X W P HX HW HP] for nblk_in
-// blocks (KA = nblk_in*k rows, KB = 2*KA columns).
-__global__ __launch_bounds__(64) void rr_kernel(int k, int nblk_in, const double *__restrict__ M,
-                                                double *__restrict__ Cout, double *__restrict__ theta,
-                                                int *__restrict__ flags, double tol) {
+// blocks (KA = nblk_in*k rows, KB = 2*KA columns).  One workgroup of
+// RR_THREADS threads; every thread owns a fixed set of matrix entries for the
+// Jacobi rounds.
+constexpr int RR_THREADS = 256;
+constexpr int RQ = (NMAX * NMAX + RR_THREADS - 1) / RR_THREADS;
+
+__device__ inline double block_total(double v, double *sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x % LOBPCG_WAVE, wave = threadIdx.x / LOBPCG_WAVE;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < RR_THREADS / LOBPCG_WAVE; ++w) t += sh[w];
+    return t;
+}
+
+__global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, const double *__restrict__ M,
+                                                        double *__restrict__ Cout, double *__restrict__ theta,
+                                                        int *__restrict__ flags, double tol) {
     __shared__ double O[NMAX * LD];
     __shared__ double A[NMAX * LD];
     __shared__ double V[NMAX * LD];
@@ -114,7 +130,8 @@ __global__ __launch_bounds__(64) void rr_kernel(int k, int nblk_in, const double
     __shared__ int idx[NMAX];
     __shared__ double rot_c[NMAX], rot_s[NMAX];
     __shared__ int partner[NMAX];
-    __shared__ int isp[NMAX];
+    __shared__ double sh[RR_THREADS / LOBPCG_WAVE];
+    __shared__ double Ys[NMAX * KM_CHOL];
     const int t = threadIdx.x;
     if (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL)) return;
     const int KA = nblk_in * k, KB = 2 * KA;
@@ -122,7 +139,7 @@ __global__ __launch_bounds__(64) void rr_kernel(int k, int nblk_in, const double
     for (;;) {
         const int N = nblk * k;
         // pencil from lower blocks; diagonal blocks symmetrised
-        for (int e = t; e < N * N; e += LOBPCG_WAVE) {
+        for (int e = t; e < N * N; e += RR_THREADS) {
             int a = e / N, b = e % N, ba = a / k, bb = b / k;
             double o, g;
             if (ba > bb) {
@@ -146,7 +163,7 @@ __global__ __launch_bounds__(64) void rr_kernel(int k, int nblk_in, const double
         __syncthreads();
         bool posdiag = true;
         for (int i = 0; i < N; ++i) posdiag = posdiag && sc[i] > 0;
-        for (int e = t; e < N * N; e += LOBPCG_WAVE) {
+        for (int e = t; e < N * N; e += RR_THREADS) {
             int a = e / N, b = e % N;
             O[a * LD + b] *= sc[a] * sc[b];
             A[a * LD + b] *= sc[a] * sc[b];
@@ -164,7 +181,7 @@ __global__ __launch_bounds__(64) void rr_kernel(int k, int nblk_in, const double
             return;
         }
         // Z = L^{-1} G (column c per thread), stored in V
-        for (int c = t; c < N; c += LOBPCG_WAVE) {
+        for (int c = t; c < N; c += RR_THREADS) {
             for (int i = 0; i < N; ++i) {
                 double v = A[i * LD + c];
                 for (int p = 0; p < i; ++p) v -= O[i * LD + p] * V[p * LD + c];
@@ -173,7 +190,7 @@ __global__ __launch_bounds__(64) void rr_kernel(int k, int nblk_in, const double
         }
         __syncthreads();
         // A = L^{-1} Z^T  (= L^{-1} G L^{-T} since G is symmetric)
-        for (int c = t; c < N; c += LOBPCG_WAVE) {
+        for (int c = t; c < N; c += RR_THREADS) {
             for (int i = 0; i < N; ++i) {
                 double v = V[c * LD + i];
                 for (int p = 0; p < i; ++p) v -= O[i * LD + p] * A[p * LD + c];
@@ -181,104 +198,85 @@ __global__ __launch_bounds__(64) void rr_kernel(int k, int nblk_in, const double
             }
         }
         __syncthreads();
+        // this thread's entries (fixed for the whole Jacobi iteration)
+        int ei[RQ], ej[RQ];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            const int e = t + RR_THREADS * q;
+            ei[q] = e < N * N ? e / N : -1;
+            ej[q] = e < N * N ? e % N : 0;
+        }
         // symmetrise, V = I
-        double regs[QMAX];
-        double vv[QMAX];
+        double ra[RQ], rv[RQ];
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
-            int e = t + LOBPCG_WAVE * q;
-            if (e < N * N) {
-                int a = e / N, b = e % N;
-                regs[q] = 0.5 * (A[a * LD + b] + A[b * LD + a]);
-            }
-        }
+        for (int q = 0; q < RQ; ++q)
+            if (ei[q] >= 0) ra[q] = 0.5 * (A[ei[q] * LD + ej[q]] + A[ej[q] * LD + ei[q]]);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
-            int e = t + LOBPCG_WAVE * q;
-            if (e < N * N) {
-                int a = e / N, b = e % N;
-                A[a * LD + b] = regs[q];
-                V[a * LD + b] = (a == b) ? 1.0 : 0.0;
+        for (int q = 0; q < RQ; ++q)
+            if (ei[q] >= 0) {
+                A[ei[q] * LD + ej[q]] = ra[q];
+                V[ei[q] * LD + ej[q]] = ei[q] == ej[q] ? 1.0 : 0.0;
             }
-        }
         __syncthreads();
-        // cyclic Jacobi, round-robin pairing over Ne = N rounded up to even
+        // cyclic Jacobi, round-robin pairing over Ne = N rounded up to even:
+        // all Ne/2 rotations of a round are disjoint and applied at once as
+        // A <- J^T A J, V <- V J, with J acting on index i as
+        // (new)_i = c_i (old)_i + s_i (old)_partner(i)
         const int Ne = N + (N & 1);
         for (int sweep = 0; sweep < 30; ++sweep) {
             double off = 0.0, tot = 0.0;
-            for (int e = t; e < N * N; e += LOBPCG_WAVE) {
-                int a = e / N, b = e % N;
-                double v = A[a * LD + b];
-                tot += v * v;
-                if (a != b) off += v * v;
-            }
-            off = wave_sum(off);
-            tot = wave_sum(tot);
+#pragma unroll
+            for (int q = 0; q < RQ; ++q)
+                if (ei[q] >= 0) {
+                    const double v = A[ei[q] * LD + ej[q]];
+                    tot += v * v;
+                    if (ei[q] != ej[q]) off += v * v;
+                }
+            off = block_total(off, sh);
+            tot = block_total(tot, sh);
             if (off <= 1e-30 * tot || off == 0.0) break;
             for (int r = 0; r < Ne - 1; ++r) {
                 if (t < Ne / 2) {
-                    int pos_p = t, pos_q = Ne - 1 - t;
+                    const int pos_p = t, pos_q = Ne - 1 - t;
                     int p = pos_p == 0 ? 0 : 1 + (pos_p - 1 + r) % (Ne - 1);
                     int q = 1 + (pos_q - 1 + r) % (Ne - 1);
                     if (p > q) { int tmp = p; p = q; q = tmp; }
-                    double c = 1.0, s = 0.0;
                     if (q < N) {
-                        double apq = A[p * LD + q];
+                        double c = 1.0, sn = 0.0;
+                        const double apq = A[p * LD + q];
                         if (apq != 0.0) {
-                            double tau = (A[q * LD + q] - A[p * LD + p]) / (2.0 * apq);
-                            double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                            const double tau = (A[q * LD + q] - A[p * LD + p]) / (2.0 * apq);
+                            const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                             c = 1.0 / sqrt(1.0 + tt * tt);
-                            s = tt * c;
+                            sn = tt * c;
                         }
                         partner[p] = q; partner[q] = p;
-                        isp[p] = 1; isp[q] = 0;
-                        rot_c[p] = c; rot_s[p] = s;
-                        rot_c[q] = c; rot_s[q] = s;
+                        rot_c[p] = c; rot_s[p] = -sn;
+                        rot_c[q] = c; rot_s[q] = sn;
                     } else if (p < N) {
-                        partner[p] = -1;
-                    }
-                }
-                __syncthreads();
-                // A <- J^T A J and V <- V J, all rotations of the round at once
-#pragma unroll
-                for (int q = 0; q < QMAX; ++q) {
-                    int e = t + LOBPCG_WAVE * q;
-                    if (e < N * N) {
-                        int i = e / N, j = e % N;
-                        int pi = partner[i], pj = partner[j];
-                        // row factors (J^T)[i][i], (J^T)[i][pi]; column factors J[j][j], J[pj][j]
-                        double ri = 1.0, rpi = 0.0, cj = 1.0, cpj = 0.0;
-                        if (pi >= 0) {
-                            ri = rot_c[i];
-                            rpi = isp[i] ? -rot_s[i] : rot_s[i];
-                        }
-                        if (pj >= 0) {
-                            cj = rot_c[j];
-                            cpj = isp[j] ? -rot_s[j] : rot_s[j];
-                        }
-                        double v = ri * cj * A[i * LD + j];
-                        if (pj >= 0) v += ri * cpj * A[i * LD + pj];
-                        if (pi >= 0) {
-                            v += rpi * cj * A[pi * LD + j];
-                            if (pj >= 0) v += rpi * cpj * A[pi * LD + pj];
-                        }
-                        regs[q] = v;
-                        double w = cj * V[i * LD + j];
-                        if (pj >= 0) w += cpj * V[i * LD + pj];
-                        vv[q] = w;
+                        partner[p] = p; rot_c[p] = 1.0; rot_s[p] = 0.0;
                     }
                 }
                 __syncthreads();
 #pragma unroll
-                for (int q = 0; q < QMAX; ++q) {
-                    int e = t + LOBPCG_WAVE * q;
-                    if (e < N * N) {
-                        int i = e / N, j = e % N;
-                        A[i * LD + j] = regs[q];
-                        V[i * LD + j] = vv[q];
+                for (int q = 0; q < RQ; ++q) {
+                    if (ei[q] >= 0) {
+                        const int i = ei[q], j = ej[q];
+                        const int pi = partner[i], pj = partner[j];
+                        const double ci = rot_c[i], si = rot_s[i], cj = rot_c[j], sj = rot_s[j];
+                        ra[q] = ci * (cj * A[i * LD + j] + sj * A[i * LD + pj]) +
+                                si * (cj * A[pi * LD + j] + sj * A[pi * LD + pj]);
+                        rv[q] = cj * V[i * LD + j] + sj * V[i * LD + pj];
                     }
                 }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < RQ; ++q)
+                    if (ei[q] >= 0) {
+                        A[ei[q] * LD + ej[q]] = ra[q];
+                        V[ei[q] * LD + ej[q]] = rv[q];
+                    }
                 __syncthreads();
             }
         }
@@ -296,13 +294,13 @@ __global__ __launch_bounds__(64) void rr_kernel(int k, int nblk_in, const double
         // C = diag(sc) L^{-T} V[:, idx[0..k)]
         if (t < k) {
             const int col = idx[t];
-            double y[NMAX];
+            double *y = Ys + t;   // column t of Ys, stride KM_CHOL
             for (int i = N - 1; i >= 0; --i) {
                 double v = V[i * LD + col];
-                for (int p = i + 1; p < N; ++p) v -= O[p * LD + i] * y[p];
-                y[i] = v / O[i * LD + i];
+                for (int p = i + 1; p < N; ++p) v -= O[p * LD + i] * y[p * KM_CHOL];
+                y[i * KM_CHOL] = v / O[i * LD + i];
             }
-            for (int i = 0; i < N; ++i) Cout[i * k + t] = sc[i] * y[i];
+            for (int i = 0; i < N; ++i) Cout[i * k + t] = sc[i] * y[i * KM_CHOL];
             theta[t] = A[col * LD + col];
         }
         if (t == 0) flags[1] = nblk;
@@ -327,7 +325,7 @@ int launch_cholinv(lobpcg_ctx *ctx, int k, const double *B, double *rinv, hipStr
 int launch_rr(lobpcg_ctx *ctx, int k, int nblk, hipStream_t s) {
     if (nblk * k > NMAX) return set_err(ctx, LOBPCG_EUNSUPPORTED, "rr: %d x %d pencil too large", nblk * k, nblk * k);
     double tol = ctx->dtype == LOBPCG_F64 ? 1e-13 : 1e-8;
-    rr_kernel<<<1, 64, 0, s>>>(k, nblk, ctx->gram_out, ctx->rr_C, ctx->rr_theta, ctx->dflags, tol);
+    rr_kernel<<<1, RR_THREADS, 0, s>>>(k, nblk, ctx->gram_out, ctx->rr_C, ctx->rr_theta, ctx->dflags, tol);
     return LOBPCG_OK;
 }
 

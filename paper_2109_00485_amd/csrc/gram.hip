@@ -72,32 +72,37 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
-    const int64_t nslab = (g.n + 15) / 16;
-    const int64_t wave_id = (int64_t)blockIdx.x * GRAM_WAVES + wave;
-    const int64_t nwaves = (int64_t)gridDim.x * GRAM_WAVES;
-    for (int64_t slab = wave_id; slab < nslab; slab += nwaves) {
+    // the 4 rows of a 16-row slab this lane supplies: r0 + 4t + lg (K = 4 per
+    // instruction, four instructions) or r0 + 4lg + t (BF16, K = 16)
+    auto row_of = [&](int64_t r0, int t) -> int64_t { return MODE == M_BF16X3 ? r0 + 4 * lg + t : r0 + 4 * t + lg; };
+    auto load = [&](int64_t slab, TI (&fa)[4][MT], TI (&fb)[4][NT]) {
         const int64_t r0 = slab * 16;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t r = row_of(r0, t);
+            const bool in = r < g.n;
+#pragma unroll
+            for (int i = 0; i < MT; ++i) fa[t][i] = (pa[i] && in) ? pa[i][r * g.wa] : TI(0);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) fb[t][j] = (pb[j] && in) ? pb[j][r * g.wb] : TI(0);
+        }
+    };
+    auto compute = [&](const TI (&fa)[4][MT], const TI (&fb)[4][NT]) {
         if constexpr (MODE == M_BF16X3) {
-            // K = 16 rows per instruction; lane group lg owns rows r0 + 4*lg + t
             s16x4 a0[MT], a1[MT], b0[NT], b1[NT];
 #pragma unroll
-            for (int i = 0; i < MT; ++i) {
+            for (int t = 0; t < 4; ++t) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    int64_t r = r0 + 4 * lg + t;
-                    float v = (pa[i] && r < g.n) ? (float)pa[i][r * g.wa] : 0.0f;
-                    unsigned short h = bf16_rne(v);
+                for (int i = 0; i < MT; ++i) {
+                    const float v = (float)fa[t][i];
+                    const unsigned short h = bf16_rne(v);
                     a0[i][t] = (short)h;
                     a1[i][t] = (short)bf16_rne(v - bf16_to_f32(h));
                 }
-            }
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    int64_t r = r0 + 4 * lg + t;
-                    float v = (pb[j] && r < g.n) ? (float)pb[j][r * g.wb] : 0.0f;
-                    unsigned short h = bf16_rne(v);
+                for (int j = 0; j < NT; ++j) {
+                    const float v = (float)fb[t][j];
+                    const unsigned short h = bf16_rne(v);
                     b0[j][t] = (short)h;
                     b1[j][t] = (short)bf16_rne(v - bf16_to_f32(h));
                 }
@@ -111,25 +116,49 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[i], b0[j], acc[i][j], 0, 0, 0);
                 }
         } else {
-            // K = 4 rows per instruction, four instructions per 16-row slab
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int64_t r = r0 + 4 * t + lg;
-                AccS av[MT], bv[NT];
-#pragma unroll
-                for (int i = 0; i < MT; ++i) av[i] = (pa[i] && r < g.n) ? (AccS)pa[i][r * g.wa] : AccS(0);
-#pragma unroll
-                for (int j = 0; j < NT; ++j) bv[j] = (pb[j] && r < g.n) ? (AccS)pb[j][r * g.wb] : AccS(0);
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int i = 0; i < MT; ++i)
 #pragma unroll
                     for (int j = 0; j < NT; ++j) {
                         if constexpr (MODE == M_F64)
-                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64((AccS)fa[t][i], (AccS)fb[t][j],
+                                                                             acc[i][j], 0, 0, 0);
                         else
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((AccS)fa[t][i], (AccS)fb[t][j],
+                                                                             acc[i][j], 0, 0, 0);
                     }
+        }
+    };
+
+    // software pipeline: the next slab's loads are in flight during this slab's MFMAs
+    const int64_t nslab = (g.n + 15) / 16;
+    const int64_t wave_id = (int64_t)blockIdx.x * GRAM_WAVES + wave;
+    const int64_t nwaves = (int64_t)gridDim.x * GRAM_WAVES;
+    TI ca[4][MT], cb[4][NT];
+    if (wave_id < nslab) load(wave_id, ca, cb);
+    for (int64_t slab = wave_id; slab < nslab; slab += nwaves) {
+        TI na[4][MT], nb[4][NT];
+        const int64_t nx = slab + nwaves;
+        if (nx < nslab) {
+            load(nx, na, nb);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+#pragma unroll
+                for (int i = 0; i < MT; ++i) na[t][i] = TI(0);
+#pragma unroll
+                for (int j = 0; j < NT; ++j) nb[t][j] = TI(0);
             }
+        }
+        compute(ca, cb);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int i = 0; i < MT; ++i) ca[t][i] = na[t][i];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) cb[t][j] = nb[t][j];
         }
     }
 
@@ -161,12 +190,31 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
     }
 }
 
-__global__ void gram_reduce_kernel(const double *__restrict__ partial, int nparts, int count,
-                                   double *__restrict__ out) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+// Stage 1: block (x, y) sums partials y*RB .. y*RB+RB-1 of outputs x*64 ..
+// x*64+63 (four wavefronts split the partials, lanes over outputs); stage 2
+// sums the stage-1 rows.  Fixed order throughout: deterministic.
+constexpr int RB = 64;
+__global__ __launch_bounds__(256) void gram_reduce1_kernel(const double *__restrict__ partial, int nparts, int count,
+                                                           double *__restrict__ stage) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int e = blockIdx.x * 64 + lane;
+    const int p0 = blockIdx.y * RB;
+    double s = 0.0;
+    if (e < count)
+        for (int p = p0 + wave; p < min(p0 + RB, nparts); p += 4) s += partial[(size_t)p * count + e];
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && e < count)
+        stage[(size_t)blockIdx.y * count + e] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+__global__ void gram_reduce2_kernel(const double *__restrict__ stage, int nstage, int count,
+                                    double *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
     double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * count + e];
+    for (int p = 0; p < nstage; ++p) s += stage[(size_t)p * count + e];
     out[e] = s;
 }
 
@@ -195,9 +243,8 @@ int launch_gram(lobpcg_ctx *ctx, const GramArgs &ga, int prec, double *out, hipS
     for (int i = 0; i < 6; ++i) g.b[i] = i < ga.nb ? ga.b[i] : nullptr;
     g.na = ga.na; g.nb = ga.nb; g.wa = ga.wa; g.wb = ga.wb; g.n = ctx->n;
     const int64_t nslab = (ctx->n + 15) / 16;
-    // enough slabs per wavefront to amortise the partial write, at most one partial per slot
-    int grid = (int)std::min<int64_t>(ctx->gram_max_wg, std::max<int64_t>(1, (nslab + 4 * GRAM_WAVES - 1) / (4 * GRAM_WAVES)));
-    grid = std::min(grid, 256);
+    // at least 4 slabs per wavefront (amortises the partial), at most one partial per slot
+    const int grid = (int)std::min<int64_t>(ctx->gram_max_wg, std::max<int64_t>(1, (nslab + 4 * GRAM_WAVES - 1) / (4 * GRAM_WAVES)));
     int rc;
     if (prec == LOBPCG_GRAM_AUTO) prec = ctx->gram;
     if (ctx->dtype == LOBPCG_F64) {
@@ -213,7 +260,12 @@ int launch_gram(lobpcg_ctx *ctx, const GramArgs &ga, int prec, double *out, hipS
         return set_err(ctx, LOBPCG_EINVAL, "gram: bad precision %d", prec);
     }
     if (rc != LOBPCG_OK) return set_err(ctx, rc, "gram: no kernel for %dx%d tiles", MT, NT);
-    gram_reduce_kernel<<<ceil_div(KA * KB, 256), 256, 0, s>>>(ctx->gram_partial, grid, KA * KB, out);
+    const int count = KA * KB;
+    const int nstage = ceil_div(grid, RB);
+    // stage-1 rows live after the partial slots (the allocation holds gram_max_wg / RB extra slots)
+    double *stage = ctx->gram_partial + (size_t)ctx->gram_max_wg * 48 * 96;
+    gram_reduce1_kernel<<<dim3(ceil_div(count, 64), nstage), 256, 0, s>>>(ctx->gram_partial, grid, count, stage);
+    gram_reduce2_kernel<<<ceil_div(count, 256), 256, 0, s>>>(stage, nstage, count, out);
     return LOBPCG_OK;
 }
 

@@ -90,7 +90,7 @@ struct lobpcg_ctx {
     // LOBPCG blocks (n x kmax each)
     void *X = nullptr, *W = nullptr, *P = nullptr, *HX = nullptr, *HW = nullptr, *HP = nullptr;
     // Gram scratch
-    double *gram_partial = nullptr;  // [gram_max_wg][48*96]
+    double *gram_partial = nullptr;  // [gram_max_wg + gram_max_wg/64 + 1][48*96]: partials, then stage-1 rows
     int gram_max_wg = 0;
     double *gram_out = nullptr;      // up to 48 x 96
     double *gram_out2 = nullptr;     // a second k x k result (Cholesky QR)

@@ -169,12 +169,22 @@ __global__ __launch_bounds__(SPMM_THREADS) void spmm_pull_kernel(
 #ifndef LOBPCG_TW_DB
 #define LOBPCG_TW_DB 0          // double-buffer the X windows
 #endif
-constexpr int TW_THREADS = 512;
+#ifndef LOBPCG_TW_GROUP
+#define LOBPCG_TW_GROUP 0       // lanes per output row in the tiled kernel (0: by block width)
+#endif
+#ifndef LOBPCG_TW_PAD
+#define LOBPCG_TW_PAD -1        // pad staged X rows by 16 bytes (-1: by block width)
+#endif
 constexpr int NBUF = LOBPCG_TW_DB ? 2 : 1;
 
 template <typename T, int KP>
 struct TwShape {
-    static constexpr int PAD = 16 / (int)sizeof(T);   // 16-byte pad: keeps row alignment, spreads banks
+    // rows of up to 32 bytes: 4 lanes per output row and unpadded staging (measured
+    // best on gfx950); wider rows: 8 lanes per row and a 16-byte pad per staged row
+    static constexpr bool NARROW = KP * (int)sizeof(T) <= 32;
+    static constexpr int TG = LOBPCG_TW_GROUP ? LOBPCG_TW_GROUP : (NARROW ? 4 : 8);
+    static constexpr int THREADS = 64 * TG;
+    static constexpr int PAD = (LOBPCG_TW_PAD < 0 ? !NARROW : LOBPCG_TW_PAD) ? 16 / (int)sizeof(T) : 0;
     static constexpr int STRIDE = KP + PAD;
     static constexpr int SLOT = 64 * STRIDE;           // elements per staged 64-row block
     // 32 KB of staged X for k <= 8 (four workgroups per CU), 64 KB for wider blocks
@@ -182,7 +192,7 @@ struct TwShape {
     static constexpr int WT0 = LDS_BYTES / NBUF / (SLOT * (int)sizeof(T));
     static constexpr int WT = WT0 < 2 ? 2 : WT0;       // slots per window
     static constexpr int VEC = 16 / (int)sizeof(T);    // elements per 16-byte load
-    static constexpr int MAXV = (WT * 64 * KP / VEC + TW_THREADS - 1) / TW_THREADS;  // 16-byte loads per thread
+    static constexpr int MAXV = (WT * 64 * KP / VEC + THREADS - 1) / THREADS;  // 16-byte loads per thread
 };
 
 // one 16-byte unit of a staged window (vector path, k == KP): slot s, block row rr, column q
@@ -198,19 +208,20 @@ __device__ inline void tw_unit(int idx, int &s, int &rr, int &q) {
 }
 
 template <typename T, int KP>
-__global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
+__global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
     int64_t n, int k, const int64_t *__restrict__ rp, const uint16_t *__restrict__ rix, const T *__restrict__ rv,
     const int64_t *__restrict__ cp, const uint16_t *__restrict__ cix, const T *__restrict__ cv,
     const int32_t *__restrict__ rlist_off, const int32_t *__restrict__ rlist,
     const int32_t *__restrict__ clist_off, const int32_t *__restrict__ clist,
     const T *__restrict__ diag, const T *__restrict__ X, T *__restrict__ Y) {
     using S = TwShape<T, KP>;
+    constexpr int TG = S::TG;
     constexpr int VEC = S::VEC;
     using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
     __shared__ int32_t s_list[TILE_SLOTS];
     __shared__ __align__(16) T Xs[NBUF * S::WT * S::SLOT];
     const int64_t I = blockIdx.x;
-    const int r = threadIdx.x / GROUP, sl = threadIdx.x % GROUP;
+    const int r = threadIdx.x / TG, sl = threadIdx.x % TG;
     const int64_t i = I * 64 + r;
     const bool valid = i < n;
     const bool vec = (k % VEC) == 0 && k == KP;
@@ -220,7 +231,7 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
     // stage window [s0, s1) into buffer b (scalar path for k not a multiple of the vector width)
     auto stage_scalar = [&](int s0, int s1, int b) {
         const int per = 64 * k;
-        for (int idx = threadIdx.x; idx < (s1 - s0) * per; idx += TW_THREADS) {
+        for (int idx = threadIdx.x; idx < (s1 - s0) * per; idx += S::THREADS) {
             const int s = idx / per, rem = idx - s * per, rr = rem / k, q = rem - rr * k;
             const int64_t grow = (int64_t)s_list[s0 + s] * 64 + rr;
             Xs[(b * S::WT + s) * S::SLOT + rr * S::STRIDE + q] = grow < n ? X[grow * k + q] : T(0);
@@ -230,7 +241,7 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
     auto fetch = [&](int s0, int s1) {   // global loads of a window into registers
 #pragma unroll
         for (int u = 0; u < S::MAXV; ++u) {
-            const int idx = threadIdx.x + u * TW_THREADS;
+            const int idx = threadIdx.x + u * S::THREADS;
             if (idx < (s1 - s0) * (64 * KP / VEC)) {
                 int s, rr, q;
                 tw_unit<T, KP>(idx, s, rr, q);
@@ -242,7 +253,7 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
     auto deposit = [&](int s0, int s1, int b) {   // registers into LDS buffer b
 #pragma unroll
         for (int u = 0; u < S::MAXV; ++u) {
-            const int idx = threadIdx.x + u * TW_THREADS;
+            const int idx = threadIdx.x + u * S::THREADS;
             if (idx < (s1 - s0) * (64 * KP / VEC)) {
                 int s, rr, q;
                 tw_unit<T, KP>(idx, s, rr, q);
@@ -258,8 +269,8 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
         const int64_t *ptr = view == 0 ? rp : cp;
         const int l0 = loff[I], nslots = loff[I + 1] - l0;
         __syncthreads();  // the previous view is done with s_list and Xs
-        for (int t = threadIdx.x; t < nslots; t += TW_THREADS) s_list[t] = list[l0 + t];
-        // this lane's chunks of its row segment: chunk m (8 entries) belongs to lane m % 8
+        for (int t = threadIdx.x; t < nslots; t += S::THREADS) s_list[t] = list[l0 + t];
+        // this lane's chunks of its row segment: chunk m (8 entries) belongs to lane m % TG
         int64_t pos = 0, seg_end = 0;
         int off = 0;   // entries of the current chunk already consumed
         if (valid) {
@@ -313,7 +324,7 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
                     if (t >= off && t < nb) axpy_row<T, KP>(acc, v[t], xb + (u[t] - base) * S::STRIDE, k);
                 off = nb;   // slots are sorted within the chunk: [old off, nb) was just consumed
                 if (off == 8) {
-                    pos += 8 * GROUP;
+                    pos += 8 * TG;
                     off = 0;
                     more = pos < seg_end;
                 } else {
@@ -338,9 +349,8 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
 #pragma unroll
     for (int q = 0; q < KP; ++q) {
         T v = acc[q];
-        v += __shfl_xor(v, 4, GROUP);
-        v += __shfl_xor(v, 2, GROUP);
-        v += __shfl_xor(v, 1, GROUP);
+#pragma unroll
+        for (int m = TG / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, TG);
         acc[q] = v;
     }
     if (!valid) return;
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(TW_THREADS) void spmm_tiled_kernel(
     T *yi = Y + i * k;
 #pragma unroll
     for (int q = 0; q < KP; ++q)
-        if (q < k && (q % GROUP) == sl) yi[q] = acc[q] + di * xi[q];
+        if (q < k && (q % TG) == sl) yi[q] = acc[q] + di * xi[q];
 }
 
 template <typename T, bool TILED>
@@ -379,11 +389,11 @@ int spmm_pull(lobpcg_ctx *ctx, const T *X, T *Y, int k, hipStream_t s) {
 #define TW_ARGS ctx->n, k, ctx->rp, tf.rix, rv, ctx->cp, tf.cix, cv, tf.rlist_off, tf.rlist, tf.clist_off, tf.clist, \
                 diag, X, Y
         if (k <= 4)
-            spmm_tiled_kernel<T, 4><<<grid, TW_THREADS, 0, s>>>(TW_ARGS);
+            spmm_tiled_kernel<T, 4><<<grid, TwShape<T, 4>::THREADS, 0, s>>>(TW_ARGS);
         else if (k <= 8)
-            spmm_tiled_kernel<T, 8><<<grid, TW_THREADS, 0, s>>>(TW_ARGS);
+            spmm_tiled_kernel<T, 8><<<grid, TwShape<T, 8>::THREADS, 0, s>>>(TW_ARGS);
         else
-            spmm_tiled_kernel<T, 16><<<grid, TW_THREADS, 0, s>>>(TW_ARGS);
+            spmm_tiled_kernel<T, 16><<<grid, TwShape<T, 16>::THREADS, 0, s>>>(TW_ARGS);
 #undef TW_ARGS
     } else {
         spmm_pull_launch<T, false>(ctx, X, Y, k, s);

@@ -21,133 +21,185 @@ __device__ inline T guard_div(T r, double dm, double eps) {
     return (T)((double)r / s);
 }
 
-// Block reduction of 2*k per-thread FP64 sums into one partial per workgroup
-// (fully unrolled so the per-thread sums stay in registers).
-__device__ inline void block_reduce_store(const double (&vals)[2][KM], int k, double *__restrict__ out) {
-    __shared__ double red[UPD_THREADS / LOBPCG_WAVE][2][KM];
-    const int lane = threadIdx.x % LOBPCG_WAVE, wave = threadIdx.x / LOBPCG_WAVE;
+// Layout of the update: a row's k outputs are split over TPR threads of QG
+// consecutive columns each (k = 8: 2 threads x 4, k = 16: 4 x 4; other k: one
+// thread per column).  Every thread reads the whole input rows it combines
+// (16-byte loads when k is fixed at compile time) and writes its QG columns.
+template <typename T, int KP>
+struct UpdShape {
+    static constexpr int QG = KP ? 4 : 1;
+};
+
+template <typename T, int KP>
+__device__ inline void load_row(const T *__restrict__ p, int k, T (&v)[KM]) {
+    if constexpr (KP > 0 && (KP * sizeof(T)) % 16 == 0) {
+        using V4 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+        constexpr int PER = 16 / sizeof(T);
+        const V4 *q = reinterpret_cast<const V4 *>(p);
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+        for (int c = 0; c < KP / PER; ++c) {
+            V4 x = q[c];
+            const T *xs = reinterpret_cast<const T *>(&x);
 #pragma unroll
-        for (int q = 0; q < KM; ++q) {
-            if (q < k) {
-                double v = vals[s][q];
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-                if (lane == 0) red[wave][s][q] = v;
-            }
+            for (int e = 0; e < PER; ++e) v[c * PER + e] = xs[e];
         }
-    __syncthreads();
-    if (threadIdx.x < 2 * k) {
-        int s = threadIdx.x / k, q = threadIdx.x % k;
-        double acc = 0.0;
-        for (int w = 0; w < UPD_THREADS / LOBPCG_WAVE; ++w) acc += red[w][s][q];
-        out[(size_t)blockIdx.x * 3 * KM + s * KM + q] = acc;
+    } else {
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (q < k) v[q] = p[q];
+    }
+}
+
+// acc[c] += sum_m row[m] * Cb[m * k + q0 + c],  c < QG
+template <typename T, int KP, int QG>
+__device__ inline void mac_cols(T (&acc)[QG], const T (&row)[KM], const T *__restrict__ Cb, int k, int q0) {
+#pragma unroll
+    for (int m = 0; m < KM; ++m) {
+        if (m < (KP ? KP : k)) {
+#pragma unroll
+            for (int c = 0; c < QG; ++c) acc[c] += row[m] * Cb[m * (KP ? KP : k) + q0 + c];
+        }
     }
 }
 
 // mode: nblk in {1,2,3} = combine with C from Rayleigh-Ritz; 0 = no combine
 // (X, HX used as they are, theta given).  nblk is read from flags[1] when
-// nblk_dev != 0 (the Rayleigh-Ritz kernel may have dropped P).
-template <typename T>
+// nblk_dev != 0 (the Rayleigh-Ritz kernel may have dropped P).  The combined
+// rows are written only after every thread of the row has read them, which
+// the row's threads guarantee by reading before writing within one
+// wavefront (TPR divides the wavefront).
+template <typename T, int KP>
 __global__ __launch_bounds__(UPD_THREADS) void update_kernel(
-    int64_t n, int k, int nblk_host, int nblk_dev, const double *__restrict__ Cg, const double *__restrict__ theta_g,
-    T *__restrict__ X, T *__restrict__ W, T *__restrict__ P, T *__restrict__ HX, T *__restrict__ HW,
-    T *__restrict__ HP, const T *__restrict__ d, int precond, double eps, int write_w,
+    int64_t n, int k_rt, int nblk_host, int nblk_dev, const double *__restrict__ Cg, const double *__restrict__ theta_g,
+    T *X, T *W, T *P, T *HX, T *HW, T *HP, const T *__restrict__ d, int precond, double eps, int write_w,
     double *__restrict__ partial, const int *__restrict__ flags) {
+    constexpr int QG = UpdShape<T, KP>::QG;
     if (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL)) return;
+    const int k = KP ? KP : k_rt;
     const int nblk = nblk_dev ? flags[1] : nblk_host;
     __shared__ T Cs[3 * KM * KM];
     __shared__ double th[KM];
+    __shared__ double red[UPD_THREADS][2][4];
     const int N = nblk * k;
     for (int e = threadIdx.x; e < N * k; e += UPD_THREADS) Cs[e] = (T)Cg[e];
     if (threadIdx.x < k) th[threadIdx.x] = theta_g[threadIdx.x];
     __syncthreads();
-    double sums[2][KM];
+    // a row's threads never straddle two wavefronts
+    const int tpr = KP ? KP / QG : k;            // threads per row
+    const int rpw = LOBPCG_WAVE / tpr;           // rows per wavefront
+    const int rpi = rpw * (UPD_THREADS / LOBPCG_WAVE);  // rows per workgroup step
+    const int lane = threadIdx.x % LOBPCG_WAVE;
+    const int rr = (threadIdx.x / LOBPCG_WAVE) * rpw + lane / tpr, g = lane % tpr;
+    const int q0 = g * QG;
+    const bool active = lane / tpr < rpw;
+    double s_r[QG], s_x[QG];
 #pragma unroll
-    for (int q = 0; q < KM; ++q) sums[0][q] = sums[1][q] = 0.0;
-
-    for (int64_t i = (int64_t)blockIdx.x * UPD_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * UPD_THREADS) {
-        T xn[KM], hn[KM], pn[KM], hpn[KM];
+    for (int c = 0; c < QG; ++c) s_r[c] = s_x[c] = 0.0;
+    T thq[QG];
+#pragma unroll
+    for (int c = 0; c < QG; ++c) thq[c] = (T)th[q0 + c];
+    for (int64_t i0 = (int64_t)blockIdx.x * rpi; i0 < n; i0 += (int64_t)gridDim.x * rpi) {
+        const int64_t i = i0 + rr;
+        if (!active || i >= n) continue;
         const int64_t o = i * k;
+        T xn[QG], hn[QG], pn[QG], hpn[QG];
         if (nblk == 0) {
 #pragma unroll
-            for (int q = 0; q < KM; ++q)
-                if (q < k) { xn[q] = X[o + q]; hn[q] = HX[o + q]; }
+            for (int c = 0; c < QG; ++c) { xn[c] = X[o + q0 + c]; hn[c] = HX[o + q0 + c]; }
         } else {
+            T r0[KM], r1[KM];
 #pragma unroll
-            for (int q = 0; q < KM; ++q) xn[q] = hn[q] = pn[q] = hpn[q] = T(0);
-            // X and HX block rows
-#pragma unroll
-            for (int m = 0; m < KM; ++m) {
-                if (m < k) {
-                    T xv = X[o + m], hv = HX[o + m];
-#pragma unroll
-                    for (int q = 0; q < KM; ++q)
-                        if (q < k) { xn[q] += xv * Cs[m * k + q]; hn[q] += hv * Cs[m * k + q]; }
-                }
-            }
+            for (int c = 0; c < QG; ++c) xn[c] = hn[c] = pn[c] = hpn[c] = T(0);
+            load_row<T, KP>(X + o, k, r0);
+            load_row<T, KP>(HX + o, k, r1);
+            mac_cols<T, KP, QG>(xn, r0, Cs, k, q0);
+            mac_cols<T, KP, QG>(hn, r1, Cs, k, q0);
             if (nblk >= 2) {
-#pragma unroll
-                for (int m = 0; m < KM; ++m) {
-                    if (m < k) {
-                        T wv = W[o + m], hv = HW[o + m];
-#pragma unroll
-                        for (int q = 0; q < KM; ++q)
-                            if (q < k) { T c = Cs[(k + m) * k + q]; pn[q] += wv * c; hpn[q] += hv * c; }
-                    }
-                }
+                load_row<T, KP>(W + o, k, r0);
+                load_row<T, KP>(HW + o, k, r1);
+                mac_cols<T, KP, QG>(pn, r0, Cs + k * k, k, q0);
+                mac_cols<T, KP, QG>(hpn, r1, Cs + k * k, k, q0);
             }
             if (nblk >= 3) {
-#pragma unroll
-                for (int m = 0; m < KM; ++m) {
-                    if (m < k) {
-                        T pv = P[o + m], hv = HP[o + m];
-#pragma unroll
-                        for (int q = 0; q < KM; ++q)
-                            if (q < k) { T c = Cs[(2 * k + m) * k + q]; pn[q] += pv * c; hpn[q] += hv * c; }
-                    }
-                }
+                load_row<T, KP>(P + o, k, r0);
+                load_row<T, KP>(HP + o, k, r1);
+                mac_cols<T, KP, QG>(pn, r0, Cs + 2 * k * k, k, q0);
+                mac_cols<T, KP, QG>(hpn, r1, Cs + 2 * k * k, k, q0);
             }
 #pragma unroll
-            for (int q = 0; q < KM; ++q)
-                if (q < k) { xn[q] += pn[q]; hn[q] += hpn[q]; }
+            for (int c = 0; c < QG; ++c) { xn[c] += pn[c]; hn[c] += hpn[c]; }
         }
         const double di = precond == LOBPCG_PRECOND_DIAG ? (double)d[i] : 0.0;
-        T wv[KM];
+        T wv[QG];
 #pragma unroll
-        for (int q = 0; q < KM; ++q) {
-            if (q < k) {
-                T r = hn[q] - xn[q] * (T)th[q];
-                sums[0][q] += (double)r * (double)r;
-                sums[1][q] += (double)xn[q] * (double)xn[q];
-                wv[q] = precond == LOBPCG_PRECOND_DIAG ? guard_div<T>(r, di - th[q], eps) : r;
-            }
+        for (int c = 0; c < QG; ++c) {
+            T r = hn[c] - xn[c] * thq[c];
+            s_r[c] += (double)r * (double)r;
+            s_x[c] += (double)xn[c] * (double)xn[c];
+            wv[c] = precond == LOBPCG_PRECOND_DIAG ? guard_div<T>(r, di - th[q0 + c], eps) : r;
         }
+        // all threads of this row (same wavefront) have read their inputs
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int q = 0; q < KM; ++q) {
-            if (q < k) {
-                if (nblk != 0) {
-                    X[o + q] = xn[q];
-                    HX[o + q] = hn[q];
-                    if (nblk >= 2) { P[o + q] = pn[q]; HP[o + q] = hpn[q]; }
-                }
-                if (write_w) W[o + q] = wv[q];
+        for (int c = 0; c < QG; ++c) {
+            if (nblk != 0) {
+                X[o + q0 + c] = xn[c];
+                HX[o + q0 + c] = hn[c];
+                if (nblk >= 2) { P[o + q0 + c] = pn[c]; HP[o + q0 + c] = hpn[c]; }
             }
+            if (write_w) W[o + q0 + c] = wv[c];
         }
     }
-    block_reduce_store(sums, k, partial);
+#pragma unroll
+    for (int c = 0; c < QG; ++c) {
+        red[threadIdx.x][0][c] = active ? s_r[c] : 0.0;
+        red[threadIdx.x][1][c] = active ? s_x[c] : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * k) {
+        const int sidx = threadIdx.x / k, q = threadIdx.x % k;
+        const int gq = q / QG, c = q % QG;
+        double acc = 0.0;
+        for (int t = 0; t < UPD_THREADS; ++t) {
+            const int l = t % LOBPCG_WAVE;
+            if (l % tpr == gq && l / tpr < rpw) acc += red[t][sidx][c];
+        }
+        partial[(size_t)blockIdx.x * 3 * KM + sidx * KM + q] = acc;
+    }
 }
 
-// report = {theta, sum r^2, sum x^2, flags, nblk}
-__global__ void finalize_kernel(int k, int nparts, const double *__restrict__ partial,
-                                const double *__restrict__ theta, const int *__restrict__ flags,
-                                Report *__restrict__ rep) {
+// report = {theta, sum r^2, sum x^2, flags, nblk}: the per-workgroup sums
+// reduced in a fixed order (strided over the threads, then a tree)
+constexpr int FIN_THREADS = 256;
+__global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(int k, int nparts, const double *__restrict__ partial,
+                                                               const double *__restrict__ theta,
+                                                               const int *__restrict__ flags,
+                                                               Report *__restrict__ rep) {
+    __shared__ double red[FIN_THREADS / LOBPCG_WAVE][2 * KM];
+    double acc[2 * KM];
+#pragma unroll
+    for (int q = 0; q < 2 * KM; ++q) acc[q] = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += FIN_THREADS) {
+        const double *row = partial + (size_t)p * 3 * KM;
+#pragma unroll
+        for (int q = 0; q < 2 * KM; ++q) acc[q] += row[q];
+    }
+    const int lane = threadIdx.x % LOBPCG_WAVE, wave = threadIdx.x / LOBPCG_WAVE;
+#pragma unroll
+    for (int q = 0; q < 2 * KM; ++q) {
+        double v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
     const int t = threadIdx.x;
-    if (t < 2 * k) {
-        int s = t / k, q = t % k;
-        double acc = 0.0;
-        for (int p = 0; p < nparts; ++p) acc += partial[(size_t)p * 3 * KM + s * KM + q];
-        if (s == 0) rep->rnorm2[q] = acc; else rep->xnorm2[q] = acc;
+    if (t < 2 * KM) {
+        double v = 0.0;
+        for (int w = 0; w < FIN_THREADS / LOBPCG_WAVE; ++w) v += red[w][t];
+        const int s = t / KM, q = t % KM;
+        if (q < k) {
+            if (s == 0) rep->rnorm2[q] = v; else rep->xnorm2[q] = v;
+        }
     }
     if (t < k) rep->theta[t] = theta[t];
     if (t == 0) {
@@ -230,15 +282,22 @@ int launch_update(lobpcg_ctx *ctx, int k, int nblk, int precond, int write_w, hi
     const int grid = grid_rows(ctx->n, ctx->norm_max_wg);
     const double eps = ctx->eps_rel * ctx->gamma;
     const int pk = precond == LOBPCG_PRECOND_DIAG ? LOBPCG_PRECOND_DIAG : LOBPCG_PRECOND_NONE;
-    if (ctx->dtype == LOBPCG_F32)
-        update_kernel<float><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, nblk, nblk > 0, ctx->rr_C, ctx->rr_theta,
-            (float *)ctx->X, (float *)ctx->W, (float *)ctx->P, (float *)ctx->HX, (float *)ctx->HW, (float *)ctx->HP,
-            (const float *)ctx->diag, pk, eps, write_w, ctx->norm_partial, ctx->dflags);
-    else
-        update_kernel<double><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, nblk, nblk > 0, ctx->rr_C, ctx->rr_theta,
-            (double *)ctx->X, (double *)ctx->W, (double *)ctx->P, (double *)ctx->HX, (double *)ctx->HW,
-            (double *)ctx->HP, (const double *)ctx->diag, pk, eps, write_w, ctx->norm_partial, ctx->dflags);
-    finalize_kernel<<<1, 64, 0, s>>>(k, grid, ctx->norm_partial, ctx->rr_theta, ctx->dflags, ctx->report_dev);
+#define UPD_LAUNCH(T, KP)                                                                                        \
+    update_kernel<T, KP><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, nblk, nblk > 0, ctx->rr_C, ctx->rr_theta,       \
+        (T *)ctx->X, (T *)ctx->W, (T *)ctx->P, (T *)ctx->HX, (T *)ctx->HW, (T *)ctx->HP, (const T *)ctx->diag, pk, \
+        eps, write_w, ctx->norm_partial, ctx->dflags)
+    if (ctx->dtype == LOBPCG_F32) {
+        if (k == 8) UPD_LAUNCH(float, 8);
+        else if (k == 16) UPD_LAUNCH(float, 16);
+        else UPD_LAUNCH(float, 0);
+    } else {
+        if (k == 8) UPD_LAUNCH(double, 8);
+        else if (k == 16) UPD_LAUNCH(double, 16);
+        else UPD_LAUNCH(double, 0);
+    }
+#undef UPD_LAUNCH
+    finalize_kernel<<<1, FIN_THREADS, 0, s>>>(k, grid, ctx->norm_partial, ctx->rr_theta, ctx->dflags,
+                                              ctx->report_dev);
     return LOBPCG_OK;
 }
 

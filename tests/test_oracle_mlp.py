@@ -112,3 +112,37 @@ def test_first_adam_step_closed_form():
     # bias-corrected first step moves every weight by -lr * g / (|g| + eps)
     np.testing.assert_allclose(q.W1 - p.W1, 1e-2 * 2.0 / (2.0 + 1e-8), rtol=1e-12)
     np.testing.assert_allclose(q.W2 - p.W2, -1e-2 * 0.3 / (0.3 + 1e-8), rtol=1e-12)
+
+
+def test_degenerate_group_has_zero_loss_and_gradient():
+    p = mlp.init_params(0)
+    rng = np.random.default_rng(2)
+    p.w3 = rng.standard_normal(64) * 0.1
+    n, k = 60, 4
+    feat = rng.standard_normal((n, 4))
+    U, T, w = rng.standard_normal(n), rng.standard_normal(n), rng.uniform(0.5, 2, n)
+    X = rng.standard_normal((n, k)) * 0.1
+    gid = np.repeat([0, 1], n // 2)
+    T0 = T.copy()
+    T0[gid == 1] = 0.0   # group 1 has no target
+    L, g = mlp.group_loss(p, feat, U, T0, w, X, gid, 2)
+    L_a, g_a = mlp.group_loss(p, feat[gid == 0], U[gid == 0], T0[gid == 0], w[gid == 0], X[gid == 0],
+                              np.zeros(n // 2, dtype=int), 1)
+    # group 1 contributes 0 to the mean over two groups and nothing to the gradient
+    assert np.isclose(L, L_a / 2, rtol=1e-13)
+    for key in g:
+        assert np.allclose(np.asarray(g[key]) * 2, np.asarray(g_a[key]), rtol=1e-12, atol=1e-15)
+
+
+def test_fp32_first_layer_exact_on_representable_inputs():
+    """With inputs on a coarse grid every FP32 first-layer sum is exact, so the
+    FP32 decision path and the FP64 path coincide bit for bit."""
+    p = mlp.init_params(5)
+    rng = np.random.default_rng(3)
+    p.W1 = mlp.bf16_round(p.W1)
+    p.b1 = np.round(rng.standard_normal(64) * 8) / 8
+    p.w3 = rng.standard_normal(64) * 0.1
+    z = np.round(rng.standard_normal((300, 4)) * 4) / 4
+    o64, _ = mlp.forward(p, z)
+    o32, _ = mlp.forward(p, z, a1_f32=True)
+    assert np.array_equal(o64, o32)
