@@ -76,6 +76,36 @@ def counter_traffic(workload, k):
         return None, f"unreadable counter summary: {e!r}"
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2109_00485_amd", "weights", "random_sym_2m.json")
+
+
+def learned_vs_diag(args):
+    """Solve time and iterations with the diagonal and with the trained network
+    preconditioner on held-out matrices of the learned-preconditioner workload
+    (n = 2e6, 50 draws per row, FP32, k = 8, nev = 5, tol 1e-6)."""
+    import paper_2109_00485_amd as L
+    from paper_2109_00485_amd import train
+    from synth import workloads as W
+    if not os.path.exists(WEIGHTS):
+        return {"error": f"no trained weights at {os.path.relpath(WEIGHTS, ROOT)}"}
+    blob, meta = train.load_params(WEIGHTS)
+    net = L.Mlp(blob)
+    a, b = (int(x) for x in args.learned_seeds.split(":"))
+    rows = []
+    for seed in range(a, b):
+        A = W.make_matrix(meta.get("workload", "random_sym_2m"), seed=seed, n=meta.get("n"), f32=True)
+        r = train.compare(A, net, k=8, nev=5, tol=1e-6)
+        rows.append(dict(seed=seed, **{k_: {kk: v[kk] for kk in ("iters", "seconds", "status", "rel")}
+                                         for k_, v in r.items()}))
+        log(f"learned vs diag, seed {seed}: diag {r['diag']['iters']} it {r['diag']['seconds']:.3f} s | "
+            f"mlp {r['mlp']['iters']} it {r['mlp']['seconds']:.3f} s")
+    di = np.mean([x["diag"]["iters"] for x in rows]); mi = np.mean([x["mlp"]["iters"] for x in rows])
+    ds = np.mean([x["diag"]["seconds"] for x in rows]); ms = np.mean([x["mlp"]["seconds"] for x in rows])
+    return dict(workload=meta.get("workload", "random_sym_2m"), seeds=args.learned_seeds, weights=os.path.relpath(WEIGHTS, ROOT),
+                diag_iters=di, mlp_iters=mi, diag_seconds=round(ds, 4), mlp_seconds=round(ms, 4),
+                speedup=round(ds / ms, 3) if ms > 0 else None, runs=rows)
+
+
 def cpu_baseline(A, k, budget_s=15.0):
     import oracle
     from synth import workloads as W
@@ -114,6 +144,10 @@ def main():
     ap.add_argument("--maxiter", type=int, default=5000)
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-diagonal preconditioner comparison")
+    ap.add_argument("--learned-seeds", default="1000:1002",
+                    help="evaluation matrices (seeds) of the learned-preconditioner workload")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only time the sparse product (profiling runs); prints one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -223,6 +257,11 @@ def main():
                      "kernel": f"spmm ({q['format']}) k={args.k}",
                      "bytes_per_launch": int(nbytes), "traffic_note": tnote},
     }
+    if not args.no_learned:
+        try:
+            out["learned_vs_diag"] = learned_vs_diag(args)
+        except Exception as e:  # reported, never silently replaced
+            out["learned_vs_diag"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(A, args.k)

@@ -179,7 +179,8 @@ int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *X, double *evals, double
  *
  * The paper's preconditioner (Section 3.4) is a shifted diagonal solve; its
  * 1 x 1-tile form is W_ij = R_ij / s(d_i - theta_j).  The learned variant keeps
- * that form and multiplies it by exp(o_ij), where o_ij is the output of a
+ * that form and multiplies it by exp(2 tanh(o_ij / 2)) (a factor in
+ * [e^-2, e^2]), where o_ij is the output of a
  * 4 -> 64 -> 64 -> 1 ReLU network of the standardised per-entry features
  *     f_ij = (d_i, theta_j, rho_i, t_i),  z = (f - mu) / sigma,
  * rho_i = sum_{j != i} |h_ij| over the full symmetric row and t_i the mean |h|
@@ -234,7 +235,7 @@ int lobpcg_mlp_fit_standardizer(lobpcg_mlp *m, const float *feat, int64_t N, voi
  *   T     the exact correction of column j at row i (its error outside span X)
  *   w     importance weight of the sampled row
  *   Xrow  row i of the block X (k values)
- * Loss of a group, u = exp(o) U, a = sum w Xrow u, u' = u - Xrow . a:
+ * Loss of a group, u = exp(2 tanh(o / 2)) U, a = sum w Xrow u, u' = u - Xrow . a:
  *   L_g = 1 - (sum w u' T)^2 / ((sum w u'^2)(sum w T^2)),
  * 0 (with zero gradient) when either sum of squares is 0; the batch loss is
  * the mean over groups.  All arrays are device memory owned by the caller. */

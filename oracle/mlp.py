@@ -3,7 +3,12 @@
 The network replaces the diagonal shift-inverse 1/s(d_i - theta_j) of the
 preconditioner (Section 3.4 with 1 x 1 tiles) by a learned per-entry scale
 
-    m_ij = exp(o_ij) / s(d_i - theta_j),   W_ij = m_ij R_ij,
+    m_ij = exp(b(o_ij)) / s(d_i - theta_j),   W_ij = m_ij R_ij,
+    b(o) = C tanh(o / C),  C = OUT_BOUND = 2,
+
+so the network can reweight an entry of the diagonal step by a factor in
+[e^-2, e^2] but never suppress or blow up a row (an unbounded exp(o) let
+trained networks zero out most rows and stall the iteration),
 
 where o_ij = f(z_ij) is a 4 -> 64 -> 64 -> 1 MLP of the standardised inputs
 z = (f - mu) / sigma, f = (d_i, theta_j, rho_i, t_i): the diagonal entry, the
@@ -18,7 +23,7 @@ accumulations and everything else are FP32 on the GPU and FP64 here.
 
 Training loss, per group g = (run, iteration, column j) of harvested rows i
 with importance weights w_i (the rows are a sample of the column):
-    u_i  = exp(o_i) U_i                 U = R / s(d - theta): the diagonal step
+    u_i  = exp(b(o_i)) U_i              U = R / s(d - theta): the diagonal step
     u'_i = u_i - x_i^T a,  a = sum_l w_l x_l u_l    (remove the span(X) part)
     L_g  = 1 - (sum w u' T)^2 / ((sum w u'^2)(sum w T^2))
 with T the exact correction of the column (its error outside span(X)).  L_g is
@@ -35,6 +40,12 @@ from dataclasses import dataclass
 import numpy as np
 
 NIN, HID = 4, 64
+OUT_BOUND = 2.0
+
+
+def bound(o):
+    """b(o) = C tanh(o / C): the log-scale the preconditioner applies."""
+    return OUT_BOUND * np.tanh(np.asarray(o, dtype=np.float64) / OUT_BOUND)
 
 
 def bf16_round(x) -> np.ndarray:
@@ -118,7 +129,7 @@ def precond_scale(p: Params, d, theta, rownorm, tilemean, eps, a1_f32: bool = Fa
     o, _ = forward(p, standardize(p, f.reshape(-1, NIN)), a1_f32=a1_f32)
     o = o.reshape(n, k)
     base = 1.0 / guard(d[:, None] - theta[None, :], eps)
-    m = np.exp(o) * base
+    m = np.exp(bound(o)) * base
     return np.where(np.isfinite(m), m, base)
 
 
@@ -129,7 +140,8 @@ def group_loss(p: Params, feat, U, T, w, X, gid, ngroups, with_grad=True, bf16=T
     """
     z = standardize(p, feat)
     o, (z, a1, h1b, a2, h2, W1b, W2b, w3b) = forward(p, z, bf16=bf16, a1_f32=a1_f32)
-    e = np.exp(o)
+    ob = bound(o)
+    e = np.exp(ob)
     u = e * U
     k = X.shape[1]
     a = np.zeros((ngroups, k))
@@ -152,7 +164,7 @@ def group_loss(p: Params, feat, U, T, w, X, gid, ngroups, with_grad=True, bf16=T
     Gx = np.zeros((ngroups, k))
     np.add.at(Gx, gid, g_up[:, None] * X)
     g_u = g_up - w * np.einsum("ij,ij->i", X, Gx[gid])
-    g_o = g_u * U * e
+    g_o = g_u * U * e * (1.0 - (ob / OUT_BOUND) ** 2)   # d b / d o = 1 - tanh^2
     # back through the network (straight-through for the BF16 roundings)
     g_w3 = h2.T @ g_o
     g_b3 = float(g_o.sum())

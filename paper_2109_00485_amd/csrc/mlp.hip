@@ -1,4 +1,5 @@
-// Learned preconditioner network 4 -> 64 -> 64 -> 1.
+// Learned preconditioner network 4 -> 64 -> 64 -> 1 (the preconditioner
+// scale is exp(2 tanh(o / 2)) / s(d - theta)).
 //
 // Inference (the preconditioner apply and lobpcg_mlp_forward) runs on the
 // matrix cores, 16 samples per wavefront step, with both hidden layers
@@ -114,7 +115,11 @@ __device__ inline float mlp_step(const LaneWeights &L, float z) {
     return p + L.b3;
 }
 
-// W = m o R with m_ij = exp(o_ij) / s(d_i - theta_j); R may alias W.
+// Log-scale applied by the preconditioner: b(o) = C tanh(o / C), C = 2, so a
+// trained network reweights the diagonal step by a factor in [e^-2, e^2].
+constexpr float OUT_BOUND = 2.0f;
+
+// W = m o R with m_ij = exp(b(o_ij)) / s(d_i - theta_j); R may alias W.
 template <typename T>
 __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int k, const float *__restrict__ P,
                                                                   const T *__restrict__ d,
@@ -142,7 +147,7 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int
         if (g == 0 && valid) {
             const double dm = f - theta[j];
             const double sg = fabs(dm) >= eps ? dm : (dm < 0 ? -eps : eps);
-            double m = exp((double)o) / sg;
+            double m = (double)expf(OUT_BOUND * tanhf(o / OUT_BOUND)) / sg;
             if (!isfinite(m)) m = 1.0 / sg;
             W[sidx] = (T)((double)R[sidx] * m);
         }
@@ -282,15 +287,16 @@ __global__ __launch_bounds__(GRP_THREADS) void group_loss_kernel(int ngroups, in
 #pragma unroll
     for (int l = 0; l < 16; ++l) a[l] = 0.0;
     // a = sum w u x
+    auto lscale = [&](int64_t s) { return (double)OUT_BOUND * tanh((double)so[s] / (double)OUT_BOUND); };
     for (int64_t s = b + threadIdx.x; s < e; s += GRP_THREADS) {
-        const double wu = (double)w[s] * exp((double)so[s]) * (double)U[s];
+        const double wu = (double)w[s] * exp(lscale(s)) * (double)U[s];
 #pragma unroll
         for (int l = 0; l < 16; ++l)
             if (l < k) a[l] += wu * (double)X[s * k + l];
     }
     block_sum<16>(a, red16);
     auto uprime = [&](int64_t s, double *u_out, double *e_out) {
-        const double ex = exp((double)so[s]);
+        const double ex = exp(lscale(s));
         const double u = ex * (double)U[s];
         double xa = 0.0;
 #pragma unroll
@@ -336,7 +342,8 @@ __global__ __launch_bounds__(GRP_THREADS) void group_loss_kernel(int ngroups, in
         for (int l = 0; l < 16; ++l)
             if (l < k) xg += (double)X[s * k + l] * gx[l];
         const double gu = gup - (double)w[s] * xg;
-        so[s] = (float)(gu * (double)U[s] * ex);
+        const double t = lscale(s) / (double)OUT_BOUND;
+        so[s] = (float)(gu * (double)U[s] * ex * (1.0 - t * t));   // db/do = 1 - tanh^2
     }
 }
 

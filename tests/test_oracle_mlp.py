@@ -146,3 +146,22 @@ def test_fp32_first_layer_exact_on_representable_inputs():
     o64, _ = mlp.forward(p, z)
     o32, _ = mlp.forward(p, z, a1_f32=True)
     assert np.array_equal(o64, o32)
+
+
+def test_bounded_scale():
+    """exp(b(o)) with b = 2 tanh(o / 2): the learned factor on the diagonal step
+    stays in [e^-2, e^2] however large the network output."""
+    p = mlp.init_params(1)
+    rng = np.random.default_rng(4)
+    p.w3 = rng.standard_normal(64) * 50.0
+    p.b3 = 3.0
+    n, k = 500, 3
+    d = rng.uniform(0, 100, n)
+    theta = np.array([-1.0, 20.0, 50.0])
+    rho, tm = rng.uniform(10, 20, n), rng.uniform(0.2, 0.4, n)
+    m = mlp.precond_scale(p, d, theta, rho, tm, eps=1e-3)
+    base = 1.0 / mlp.guard(d[:, None] - theta[None, :], 1e-3)
+    r = m / base
+    assert np.all(r >= np.exp(-2.0) * (1 - 1e-12)) and np.all(r <= np.exp(2.0) * (1 + 1e-12))
+    assert r.max() > 5.0 and r.min() < 0.2        # the bound is actually reached here
+    assert np.allclose(mlp.bound([0.0, 1e9, -1e9]), [0.0, 2.0, -2.0])
