@@ -124,14 +124,15 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
                                                         double *__restrict__ Cout, double *__restrict__ theta,
                                                         int *__restrict__ flags, double tol) {
     __shared__ double O[NMAX * LD];
-    __shared__ double A[NMAX * LD];
-    __shared__ double V[NMAX * LD];
+    __shared__ double Abuf[2][NMAX * LD];   // Jacobi rounds alternate between two copies
+    __shared__ double Vbuf[2][NMAX * LD];
     __shared__ double sc[NMAX];
     __shared__ int idx[NMAX];
     __shared__ double rot_c[NMAX], rot_s[NMAX];
     __shared__ int partner[NMAX];
     __shared__ double sh[RR_THREADS / LOBPCG_WAVE];
     __shared__ double Ys[NMAX * KM_CHOL];
+    double *A = Abuf[0], *V = Vbuf[0];
     const int t = threadIdx.x;
     if (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL)) return;
     const int KA = nblk_in * k, KB = 2 * KA;
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
             ej[q] = e < N * N ? e % N : 0;
         }
         // symmetrise, V = I
-        double ra[RQ], rv[RQ];
+        double ra[RQ];
 #pragma unroll
         for (int q = 0; q < RQ; ++q)
             if (ei[q] >= 0) ra[q] = 0.5 * (A[ei[q] * LD + ej[q]] + A[ej[q] * LD + ei[q]]);
@@ -235,7 +236,9 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
                 }
             off = block_total(off, sh);
             tot = block_total(tot, sh);
-            if (off <= 1e-30 * tot || off == 0.0) break;
+            // stop at an off-diagonal norm of 1e-13 of the matrix norm: below that the
+            // rounding of the two-sided updates keeps it from shrinking further
+            if (off <= 1e-26 * tot || off == 0.0) break;
             for (int r = 0; r < Ne - 1; ++r) {
                 if (t < Ne / 2) {
                     const int pos_p = t, pos_q = Ne - 1 - t;
@@ -259,24 +262,22 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
                     }
                 }
                 __syncthreads();
+                // read the current copies, write the other ones (no write-back pass)
+                double *An = (A == Abuf[0]) ? Abuf[1] : Abuf[0];
+                double *Vn = (V == Vbuf[0]) ? Vbuf[1] : Vbuf[0];
 #pragma unroll
                 for (int q = 0; q < RQ; ++q) {
                     if (ei[q] >= 0) {
                         const int i = ei[q], j = ej[q];
                         const int pi = partner[i], pj = partner[j];
                         const double ci = rot_c[i], si = rot_s[i], cj = rot_c[j], sj = rot_s[j];
-                        ra[q] = ci * (cj * A[i * LD + j] + sj * A[i * LD + pj]) +
-                                si * (cj * A[pi * LD + j] + sj * A[pi * LD + pj]);
-                        rv[q] = cj * V[i * LD + j] + sj * V[i * LD + pj];
+                        An[i * LD + j] = ci * (cj * A[i * LD + j] + sj * A[i * LD + pj]) +
+                                         si * (cj * A[pi * LD + j] + sj * A[pi * LD + pj]);
+                        Vn[i * LD + j] = cj * V[i * LD + j] + sj * V[i * LD + pj];
                     }
                 }
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < RQ; ++q)
-                    if (ei[q] >= 0) {
-                        A[ei[q] * LD + ej[q]] = ra[q];
-                        V[ei[q] * LD + ej[q]] = rv[q];
-                    }
+                A = An;
+                V = Vn;
                 __syncthreads();
             }
         }

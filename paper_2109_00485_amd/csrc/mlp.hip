@@ -90,6 +90,10 @@ __device__ inline void load_lane_weights(LaneWeights &L, const float *__restrict
     L.isg = 1.0 / (double)P[OFF_SIG + g];
 }
 
+// relu as one integer max on the bit pattern: negative floats (sign bit set)
+// compare below 0 (IEEE-mode fmaxf costs a NaN-quieting max as well)
+__device__ inline float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 // Network output for the 16 samples of one step; z is feature g of sample c.
 // Every lane returns o of its sample c.  All 64 lanes must be active.
 __device__ inline float mlp_step(const LaneWeights &L, float z) {
@@ -100,7 +104,7 @@ __device__ inline float mlp_step(const LaneWeights &L, float z) {
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int t = 0; t < 8; ++t) h[kb][t] = (__bf16)fmaxf(a1[2 * kb + t / 4][t & 3], 0.0f);
+        for (int t = 0; t < 8; ++t) h[kb][t] = (__bf16)relu(a1[2 * kb + t / 4][t & 3]);
     float p = 0.0f;
 #pragma unroll
     for (int vb = 0; vb < 4; ++vb) {
@@ -108,7 +112,7 @@ __device__ inline float mlp_step(const LaneWeights &L, float z) {
         a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.w2[vb][0], h[0], a2, 0, 0, 0);
         a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(L.w2[vb][1], h[1], a2, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) p = fmaf(L.w3[vb][r], fmaxf(a2[r], 0.0f), p);
+        for (int r = 0; r < 4; ++r) p = fmaf(L.w3[vb][r], relu(a2[r]), p);
     }
     p += __shfl_xor(p, 16);
     p += __shfl_xor(p, 32);
@@ -120,37 +124,56 @@ __device__ inline float mlp_step(const LaneWeights &L, float z) {
 constexpr float OUT_BOUND = 2.0f;
 
 // W = m o R with m_ij = exp(b(o_ij)) / s(d_i - theta_j); R may alias W.
-template <typename T>
-__global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int k, const float *__restrict__ P,
+// KP > 0 fixes k at compile time (the sample -> (row, column) split is a shift).
+// The next step's inputs are loaded before this step's matrix-core work, so
+// every wave keeps one step of loads in flight.
+template <typename T, int KP>
+__global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int k_rt, const float *__restrict__ P,
                                                                   const T *__restrict__ d,
                                                                   const float *__restrict__ rho,
                                                                   const float *__restrict__ tmean,
                                                                   const double *__restrict__ theta, const T *R, T *W,
                                                                   double eps) {
     const int lane = threadIdx.x % LOBPCG_WAVE, c = lane % 16, g = lane / 16;
+    const int k = KP ? KP : k_rt;
     LaneWeights L;
     load_lane_weights(L, P, c, g);
     const int64_t total = n * k, nsteps = (total + 15) / 16;
     const int64_t wave = ((int64_t)blockIdx.x * INF_THREADS + threadIdx.x) / LOBPCG_WAVE;
     const int64_t nwaves = (int64_t)gridDim.x * (INF_THREADS / LOBPCG_WAVE);
-    for (int64_t st = wave; st < nsteps; st += nwaves) {
+    // inputs of one step: this lane's feature; for lane group 0 also theta_j and R_ij
+    struct In {
+        double f, th;
+        T r;
+    };
+    auto load = [&](int64_t st, In &x) {
         const int64_t sidx = st * 16 + c;
         const bool valid = sidx < total;
         const int64_t i = valid ? sidx / k : 0;
         const int j = valid ? (int)(sidx - i * k) : 0;
-        double f;
-        if (g == 0) f = (double)d[i];
-        else if (g == 1) f = theta[j];
-        else if (g == 2) f = (double)rho[i];
-        else f = (double)tmean[i];
-        const float o = mlp_step(L, (float)((f - L.mu) * L.isg));
-        if (g == 0 && valid) {
-            const double dm = f - theta[j];
+        if (g == 0) x.f = (double)d[i];
+        else if (g == 1) x.f = theta[j];
+        else if (g == 2) x.f = (double)rho[i];
+        else x.f = (double)tmean[i];
+        if (g == 0) {
+            x.th = theta[j];
+            x.r = valid ? R[sidx] : T(0);
+        }
+    };
+    In cur{}, nxt{};
+    if (wave < nsteps) load(wave, cur);
+    for (int64_t st = wave; st < nsteps; st += nwaves) {
+        if (st + nwaves < nsteps) load(st + nwaves, nxt);
+        const float o = mlp_step(L, (float)((cur.f - L.mu) * L.isg));
+        const int64_t sidx = st * 16 + c;
+        if (g == 0 && sidx < total) {
+            const double dm = cur.f - cur.th;
             const double sg = fabs(dm) >= eps ? dm : (dm < 0 ? -eps : eps);
             double m = (double)expf(OUT_BOUND * tanhf(o / OUT_BOUND)) / sg;
             if (!isfinite(m)) m = 1.0 / sg;
-            W[sidx] = (T)((double)R[sidx] * m);
+            W[sidx] = (T)((double)cur.r * m);
         }
+        cur = nxt;
     }
 }
 
@@ -163,12 +186,17 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_forward_kernel(int64_t N, con
     const int64_t nsteps = (N + 15) / 16;
     const int64_t wave = ((int64_t)blockIdx.x * INF_THREADS + threadIdx.x) / LOBPCG_WAVE;
     const int64_t nwaves = (int64_t)gridDim.x * (INF_THREADS / LOBPCG_WAVE);
-    for (int64_t st = wave; st < nsteps; st += nwaves) {
+    auto load = [&](int64_t st) -> double {
         const int64_t sidx = st * 16 + c;
-        const bool valid = sidx < N;
-        const double f = valid ? (double)feat[sidx * 4 + g] : 0.0;
-        const float o = mlp_step(L, (float)((f - L.mu) * L.isg));
-        if (g == 0 && valid) out[sidx] = o;
+        return sidx < N ? (double)feat[sidx * 4 + g] : 0.0;
+    };
+    double cur = wave < nsteps ? load(wave) : 0.0;
+    for (int64_t st = wave; st < nsteps; st += nwaves) {
+        const double nxt = st + nwaves < nsteps ? load(st + nwaves) : 0.0;   // in flight during this step
+        const float o = mlp_step(L, (float)((cur - L.mu) * L.isg));
+        const int64_t sidx = st * 16 + c;
+        if (g == 0 && sidx < N) out[sidx] = o;
+        cur = nxt;
     }
 }
 
@@ -596,15 +624,20 @@ int mlp_precond_ready(lobpcg_ctx *ctx) {
 int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s) {
     const double eps = ctx->eps_rel * ctx->gamma;
     const int grid = inference_grid(ctx->n * k);
-    if (ctx->dtype == LOBPCG_F32)
-        mlp_precond_kernel<float><<<grid, INF_THREADS, 0, s>>>(ctx->n, k, ctx->mlp->params, (const float *)ctx->diag,
-                                                               ctx->feat_rownorm, ctx->feat_tilemean, theta,
-                                                               (const float *)R, (float *)W, eps);
-    else
-        mlp_precond_kernel<double><<<grid, INF_THREADS, 0, s>>>(ctx->n, k, ctx->mlp->params,
-                                                                (const double *)ctx->diag, ctx->feat_rownorm,
-                                                                ctx->feat_tilemean, theta, (const double *)R,
-                                                                (double *)W, eps);
+#define MLP_LAUNCH(T, KP)                                                                                 \
+    mlp_precond_kernel<T, KP><<<grid, INF_THREADS, 0, s>>>(ctx->n, k, ctx->mlp->params, (const T *)ctx->diag, \
+                                                           ctx->feat_rownorm, ctx->feat_tilemean, theta,     \
+                                                           (const T *)R, (T *)W, eps)
+    if (ctx->dtype == LOBPCG_F32) {
+        if (k == 8) MLP_LAUNCH(float, 8);
+        else if (k == 16) MLP_LAUNCH(float, 16);
+        else MLP_LAUNCH(float, 0);
+    } else {
+        if (k == 8) MLP_LAUNCH(double, 8);
+        else if (k == 16) MLP_LAUNCH(double, 16);
+        else MLP_LAUNCH(double, 0);
+    }
+#undef MLP_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_err(ctx, LOBPCG_EHIP, "MLP preconditioner launch: %s", hipGetErrorString(e));
     return LOBPCG_OK;

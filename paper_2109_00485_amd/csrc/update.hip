@@ -208,13 +208,18 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(int k, int nparts
     }
 }
 
-// out_i = sum_b coef_b * in_b,i * M_b   (M_b = identity when null), in place allowed
-template <typename T>
-__global__ __launch_bounds__(UPD_THREADS) void combine_kernel(int64_t n, int k, int nin, const T *in0, const T *in1,
+// out_i = sum_b coef_b * in_b,i * M_b   (M_b = identity when null), in place
+// allowed (out may alias an input: a row's threads share one wavefront and
+// read the whole row before any of them writes).  Same thread layout as the
+// update kernel.
+template <typename T, int KP>
+__global__ __launch_bounds__(UPD_THREADS) void combine_kernel(int64_t n, int k_rt, int nin, const T *in0, const T *in1,
                                                               const T *in2, const double *m0, const double *m1,
                                                               const double *m2, double c0, double c1, double c2,
                                                               T *out, const int *__restrict__ flags) {
+    constexpr int QG = UpdShape<T, KP>::QG;
     if (flags && (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL))) return;
+    const int k = KP ? KP : k_rt;
     __shared__ T Ms[3][KM * KM];
     const T *ins[3] = {in0, in1, in2};
     const double *ms[3] = {m0, m1, m2};
@@ -223,25 +228,27 @@ __global__ __launch_bounds__(UPD_THREADS) void combine_kernel(int64_t n, int k, 
         for (int e = threadIdx.x; e < k * k; e += UPD_THREADS)
             Ms[b][e] = (T)(cs[b] * (ms[b] ? ms[b][e] : ((e / k) == (e % k) ? 1.0 : 0.0)));
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * UPD_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * UPD_THREADS) {
-        T acc[KM];
+    const int tpr = KP ? KP / QG : k;
+    const int rpw = LOBPCG_WAVE / tpr;
+    const int rpi = rpw * (UPD_THREADS / LOBPCG_WAVE);
+    const int lane = threadIdx.x % LOBPCG_WAVE;
+    const int rr = (threadIdx.x / LOBPCG_WAVE) * rpw + lane / tpr, g = lane % tpr;
+    const int q0 = g * QG;
+    const bool active = lane / tpr < rpw;
+    for (int64_t i0 = (int64_t)blockIdx.x * rpi; i0 < n; i0 += (int64_t)gridDim.x * rpi) {
+        const int64_t i = i0 + rr;
+        if (!active || i >= n) continue;
+        T acc[QG];
 #pragma unroll
-        for (int q = 0; q < KM; ++q) acc[q] = T(0);
+        for (int c = 0; c < QG; ++c) acc[c] = T(0);
         for (int b = 0; b < nin; ++b) {
-            const T *src = ins[b] + i * k;
-#pragma unroll
-            for (int m = 0; m < KM; ++m) {
-                if (m < k) {
-                    T v = src[m];
-#pragma unroll
-                    for (int q = 0; q < KM; ++q)
-                        if (q < k) acc[q] += v * Ms[b][m * k + q];
-                }
-            }
+            T row[KM];
+            load_row<T, KP>(ins[b] + i * k, k, row);
+            mac_cols<T, KP, QG>(acc, row, Ms[b], k, q0);
         }
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int q = 0; q < KM; ++q)
-            if (q < k) out[i * k + q] = acc[q];
+        for (int c = 0; c < QG; ++c) out[i * k + q0 + c] = acc[c];
     }
 }
 
@@ -307,12 +314,19 @@ int launch_combine(lobpcg_ctx *ctx, int k, int nin, const void *const *in, const
     const void *i0 = in[0], *i1 = nin > 1 ? in[1] : nullptr, *i2 = nin > 2 ? in[2] : nullptr;
     const double *m0 = mats[0], *m1 = nin > 1 ? mats[1] : nullptr, *m2 = nin > 2 ? mats[2] : nullptr;
     double c0 = coef[0], c1 = nin > 1 ? coef[1] : 0.0, c2 = nin > 2 ? coef[2] : 0.0;
-    if (ctx->dtype == LOBPCG_F32)
-        combine_kernel<float><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, nin, (const float *)i0, (const float *)i1,
-            (const float *)i2, m0, m1, m2, c0, c1, c2, (float *)out, ctx->dflags);
-    else
-        combine_kernel<double><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, nin, (const double *)i0, (const double *)i1,
-            (const double *)i2, m0, m1, m2, c0, c1, c2, (double *)out, ctx->dflags);
+#define CMB_LAUNCH(T, KP)                                                                                   \
+    combine_kernel<T, KP><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, nin, (const T *)i0, (const T *)i1,          \
+                                                       (const T *)i2, m0, m1, m2, c0, c1, c2, (T *)out, ctx->dflags)
+    if (ctx->dtype == LOBPCG_F32) {
+        if (k == 8) CMB_LAUNCH(float, 8);
+        else if (k == 16) CMB_LAUNCH(float, 16);
+        else CMB_LAUNCH(float, 0);
+    } else {
+        if (k == 8) CMB_LAUNCH(double, 8);
+        else if (k == 16) CMB_LAUNCH(double, 16);
+        else CMB_LAUNCH(double, 0);
+    }
+#undef CMB_LAUNCH
     return LOBPCG_OK;
 }
 
