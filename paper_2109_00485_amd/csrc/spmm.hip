@@ -15,11 +15,12 @@
 // views together hold the full symmetric row, so the upper triangle's
 // front-heavy rows and back-heavy columns even out.
 //
-// Mapping: a group of 8 lanes owns one output row; the lanes take every 8th
-// entry of the row's two segments (8 consecutive entries per group and step),
-// each lane gathers the full k-vector X_j with 16-byte loads and accumulates k
-// partial sums in registers; the 8 partials are combined with lane shuffles at
-// the end.
+// Mapping (CSR kernel): a group of 8 lanes owns one output row; the lanes take
+// every 8th entry of the row's two segments, each lane gathers the full
+// k-vector X_j with 16-byte loads and accumulates k partial sums in registers;
+// the 8 partials are combined with lane shuffles at the end.  The tiled kernel
+// (below) keeps the 8 lanes per row but takes 4-entry chunks of the padded
+// segments and reads X from blocks staged in LDS.
 #include <algorithm>
 #include <thread>
 #include <vector>
@@ -170,7 +171,10 @@ __global__ __launch_bounds__(SPMM_THREADS) void spmm_pull_kernel(
 #define LOBPCG_TW_DB 0          // double-buffer the X windows
 #endif
 #ifndef LOBPCG_TW_GROUP
-#define LOBPCG_TW_GROUP 0       // lanes per output row in the tiled kernel (0: by block width)
+#define LOBPCG_TW_GROUP 0       // lanes per output row in the tiled kernel (0: 8)
+#endif
+#ifndef LOBPCG_TW_CHUNK
+#define LOBPCG_TW_CHUNK 4       // entries a lane takes per step (4 or 8)
 #endif
 #ifndef LOBPCG_TW_PAD
 #define LOBPCG_TW_PAD -1        // pad staged X rows by 16 bytes (-1: by block width)
@@ -179,11 +183,13 @@ constexpr int NBUF = LOBPCG_TW_DB ? 2 : 1;
 
 template <typename T, int KP>
 struct TwShape {
-    // rows of up to 32 bytes: 4 lanes per output row and unpadded staging (measured
-    // best on gfx950); wider rows: 8 lanes per row and a 16-byte pad per staged row
+    // 8 lanes per output row taking 4-entry chunks; rows of up to 32 bytes are
+    // staged unpadded, wider rows with a 16-byte pad (measured best on gfx950)
     static constexpr bool NARROW = KP * (int)sizeof(T) <= 32;
-    static constexpr int TG = LOBPCG_TW_GROUP ? LOBPCG_TW_GROUP : (NARROW ? 4 : 8);
+    static constexpr int TG = LOBPCG_TW_GROUP ? LOBPCG_TW_GROUP : 8;
     static constexpr int THREADS = 64 * TG;
+    // entries per chunk (segments are padded to 8, so 8 or 4)
+    static constexpr int CH = LOBPCG_TW_CHUNK;
     static constexpr int PAD = (LOBPCG_TW_PAD < 0 ? !NARROW : LOBPCG_TW_PAD) ? 16 / (int)sizeof(T) : 0;
     static constexpr int STRIDE = KP + PAD;
     static constexpr int SLOT = 64 * STRIDE;           // elements per staged 64-row block
@@ -270,11 +276,11 @@ __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
         const int l0 = loff[I], nslots = loff[I + 1] - l0;
         __syncthreads();  // the previous view is done with s_list and Xs
         for (int t = threadIdx.x; t < nslots; t += S::THREADS) s_list[t] = list[l0 + t];
-        // this lane's chunks of its row segment: chunk m (8 entries) belongs to lane m % TG
+        // this lane's chunks of its row segment: chunk m (CH entries) belongs to lane m % TG
         int64_t pos = 0, seg_end = 0;
         int off = 0;   // entries of the current chunk already consumed
         if (valid) {
-            pos = ptr[i] + 8 * sl;
+            pos = ptr[i] + S::CH * sl;
             seg_end = ptr[i + 1];
         }
         __syncthreads();
@@ -295,18 +301,27 @@ __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
             if (NBUF == 2 && vec && n0 < n1) fetch(n0, n1);   // next window in flight during this one
             bool more = pos < seg_end;
             while (more) {
-                const uint4 uu = *reinterpret_cast<const uint4 *>(ix + pos);
-                unsigned u[8] = {uu.x & 0xFFFFu, uu.x >> 16, uu.y & 0xFFFFu, uu.y >> 16,
-                                 uu.z & 0xFFFFu, uu.z >> 16, uu.w & 0xFFFFu, uu.w >> 16};
-                T v[8];
+                constexpr int CH = S::CH;
+                unsigned u[CH];
+                if constexpr (CH == 8) {
+                    const uint4 uu = *reinterpret_cast<const uint4 *>(ix + pos);
+                    const unsigned w4[4] = {uu.x, uu.y, uu.z, uu.w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) { u[2 * h] = w4[h] & 0xFFFFu; u[2 * h + 1] = w4[h] >> 16; }
+                } else {
+                    const uint2 uu = *reinterpret_cast<const uint2 *>(ix + pos);
+                    u[0] = uu.x & 0xFFFFu; u[1] = uu.x >> 16; u[2] = uu.y & 0xFFFFu; u[3] = uu.y >> 16;
+                }
+                T v[CH];
                 if constexpr (sizeof(T) == 4) {
-                    const float4 a = *reinterpret_cast<const float4 *>(vals + pos);
-                    const float4 c = *reinterpret_cast<const float4 *>(vals + pos + 4);
-                    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-                    v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+#pragma unroll
+                    for (int h = 0; h < CH / 4; ++h) {
+                        const float4 a = *reinterpret_cast<const float4 *>(vals + pos + 4 * h);
+                        v[4 * h] = a.x; v[4 * h + 1] = a.y; v[4 * h + 2] = a.z; v[4 * h + 3] = a.w;
+                    }
                 } else {
 #pragma unroll
-                    for (int h = 0; h < 4; ++h) {
+                    for (int h = 0; h < CH / 2; ++h) {
                         const double2 a = *reinterpret_cast<const double2 *>(vals + pos + 2 * h);
                         v[2 * h] = a.x;
                         v[2 * h + 1] = a.y;
@@ -318,13 +333,13 @@ __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
                 const T *xb = &Xs[b * S::WT * S::SLOT];
                 int nb = 0;
 #pragma unroll
-                for (int t = 0; t < 8; ++t) nb += u[t] < lim ? 1 : 0;
+                for (int t = 0; t < CH; ++t) nb += u[t] < lim ? 1 : 0;
 #pragma unroll
-                for (int t = 0; t < 8; ++t)
+                for (int t = 0; t < CH; ++t)
                     if (t >= off && t < nb) axpy_row<T, KP>(acc, v[t], xb + (u[t] - base) * S::STRIDE, k);
                 off = nb;   // slots are sorted within the chunk: [old off, nb) was just consumed
-                if (off == 8) {
-                    pos += 8 * TG;
+                if (off == CH) {
+                    pos += CH * TG;
                     off = 0;
                     more = pos < seg_end;
                 } else {
