@@ -156,7 +156,7 @@ def main():
                     help="with --spmm-only: also run a plain 2 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (there is no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -30,7 +30,7 @@ with T the exact correction of the column (its error outside span(X)).  L_g is
 invariant to the scale of the direction, which the Rayleigh-Ritz step does not
 see either; the loss is the mean over groups.  A group with sum w u'^2 = 0 or
 sum w T^2 = 0 has no defined angle and contributes 0 with zero gradient.  Parity of what the trained
-network gains is unpinned: it is judged by iteration counts, not by a
+network gains is unpinned: it is measured by iteration counts, not by a
 reference.
 """
 from __future__ import annotations

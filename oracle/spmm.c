@@ -62,7 +62,7 @@ void oracle_mat_free(oracle_mat *m) {
     free(m->rp); free(m->ci); free(m->v); free(m->cp); free(m->ri); free(m->cv); free(m);
 }
 
-/* Y = H X (use_abs = 0) or Y = |H| |X| (use_abs = 1, the scale used to judge rounding error) */
+/* Y = H X (use_abs = 0) or Y = |H| |X| (use_abs = 1, the scale that bounds rounding error) */
 static void spmm_impl(const oracle_mat *m, int64_t k, const double *X, double *Y, int use_abs) {
     const int64_t n = m->n;
     /* pass 1: the stored part, row by row */

@@ -151,10 +151,16 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int
         const bool valid = sidx < total;
         const int64_t i = valid ? sidx / k : 0;
         const int j = valid ? (int)(sidx - i * k) : 0;
-        if (g == 0) x.f = (double)d[i];
-        else if (g == 1) x.f = theta[j];
-        else if (g == 2) x.f = (double)rho[i];
-        else x.f = (double)tmean[i];
+        if constexpr (sizeof(T) == 4) {
+            // the three per-row features are float arrays: one load through a selected pointer
+            const float *src = g == 0 ? (const float *)d : (g == 2 ? rho : tmean);
+            x.f = g == 1 ? theta[j] : (double)src[i];
+        } else {
+            if (g == 0) x.f = (double)d[i];
+            else if (g == 1) x.f = theta[j];
+            else if (g == 2) x.f = (double)rho[i];
+            else x.f = (double)tmean[i];
+        }
         if (g == 0) {
             x.th = theta[j];
             x.r = valid ? R[sidx] : T(0);
@@ -169,9 +175,17 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int
         if (g == 0 && sidx < total) {
             const double dm = cur.f - cur.th;
             const double sg = fabs(dm) >= eps ? dm : (dm < 0 ? -eps : eps);
-            double m = (double)expf(OUT_BOUND * tanhf(o / OUT_BOUND)) / sg;
-            if (!isfinite(m)) m = 1.0 / sg;
-            W[sidx] = (T)((double)cur.r * m);
+            const float e = expf(OUT_BOUND * tanhf(o / OUT_BOUND));
+            if constexpr (sizeof(T) == 4) {
+                // FP32 blocks: the scale in FP32 (the guard decision stays in FP64)
+                float m = e / (float)sg;
+                if (!isfinite(m)) m = 1.0f / (float)sg;
+                W[sidx] = cur.r * m;
+            } else {
+                double m = (double)e / sg;
+                if (!isfinite(m)) m = 1.0 / sg;
+                W[sidx] = cur.r * m;
+            }
         }
         cur = nxt;
     }
