@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tiled_2m")
+    ap.add_argument("--n", type=int, default=None,
+                    help="generate the workload's recipe at this n instead of its own (scaled runs)")
     ap.add_argument("--k", type=int, default=8)
     ap.add_argument("--nev", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -166,7 +168,7 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     t0 = time.time()
-    A = W.make_matrix(args.workload, seed=0)
+    A = W.make_matrix(args.workload, seed=0, n=args.n)
     log(f"generated {args.workload}: n={A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
     f32 = A.val.dtype == np.float32
     t0 = time.time()
@@ -192,7 +194,8 @@ def main():
     spmm_ms = s0.elapsed_time(s1) / args.spmm_reps
     log(f"standalone spmm: {spmm_ms:.3f} ms, {nbytes / spmm_ms / 1e6:.1f} GB/s")
     if args.spmm_only:
-        out = {"mode": "spmm-only", "workload": args.workload, "k": args.k, "reps": args.spmm_reps,
+        out = {"mode": "spmm-only", "workload": args.workload, "n": A.n, "nnz_stored": A.nnz, "format": q["format"],
+               "k": args.k, "reps": args.spmm_reps,
                "spmm_ms": round(spmm_ms, 4), "gbs": round(nbytes / spmm_ms / 1e6, 2), "bytes": int(nbytes)}
         if args.copy_calibration:
             # a plain copy kernel of known size: reads 2 GiB, writes 2 GiB (8x the

@@ -10,6 +10,7 @@
 #include "lobpcg.h"
 
 #define LOBPCG_WAVE 64
+#define HEAVY_ROW 1024
 
 // Device-side error flags raised by validation and by the dense kernels.
 enum : int {
@@ -105,6 +106,11 @@ struct lobpcg_ctx {
     int *dflags = nullptr;
     lobpcg_mlp *mlp = nullptr;
     unsigned long long *harvest_counter = nullptr;
+    // CSR rows whose two segments together exceed HEAVY_ROW entries: each gets a
+    // whole workgroup in a second kernel (power-law rows would otherwise hold
+    // one 8-lane group for their whole length)
+    int32_t *heavy_rows = nullptr;
+    int64_t n_heavy = 0;
     hipEvent_t ev[8] = {};
     std::string err;
 };

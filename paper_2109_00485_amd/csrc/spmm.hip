@@ -133,6 +133,10 @@ __global__ __launch_bounds__(SPMM_THREADS) void spmm_pull_kernel(
     const int64_t i = (int64_t)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / GROUP;
     const int sl = threadIdx.x % GROUP;
     if (i >= n) return;  // whole groups leave together; no barrier follows
+    if constexpr (!TILED) {
+        // long rows belong to spmm_heavy_kernel (the same predicate decides there)
+        if ((rp[i + 1] - rp[i]) + (cp[i + 1] - cp[i]) > HEAVY_ROW) return;
+    }
     T acc[KP];
 #pragma unroll
     for (int q = 0; q < KP; ++q) acc[q] = T(0);
@@ -164,6 +168,40 @@ __global__ __launch_bounds__(SPMM_THREADS) void spmm_pull_kernel(
 // index load and two 16-byte value loads; a chunk that straddles a window
 // boundary is read again (from cache) in the next window.  Entries are sorted
 // by slot, so what a lane consumes of a chunk is always a contiguous run.
+// One workgroup per long CSR row (both segments longer than HEAVY_ROW in
+// total): the threads stride over the row's entries, each keeps k partial
+// sums, and a fixed-order block reduction writes Y_i.
+constexpr int HEAVY_THREADS = 256;
+template <typename T, int KP>
+__global__ __launch_bounds__(HEAVY_THREADS) void spmm_heavy_kernel(
+    int k, const int32_t *__restrict__ rows, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const T *__restrict__ rv, const int64_t *__restrict__ cp, const int32_t *__restrict__ cri,
+    const T *__restrict__ cv, const T *__restrict__ diag, const T *__restrict__ X, T *__restrict__ Y) {
+    __shared__ T red[HEAVY_THREADS / LOBPCG_WAVE][KP];
+    const int64_t i = rows[blockIdx.x];
+    T acc[KP];
+#pragma unroll
+    for (int q = 0; q < KP; ++q) acc[q] = T(0);
+    for (int64_t e = rp[i] + threadIdx.x; e < rp[i + 1]; e += HEAVY_THREADS)
+        axpy_row<T, KP>(acc, rv[e], X + (int64_t)ci[e] * k, k);
+    for (int64_t e = cp[i] + threadIdx.x; e < cp[i + 1]; e += HEAVY_THREADS)
+        axpy_row<T, KP>(acc, cv[e], X + (int64_t)cri[e] * k, k);
+    const int lane = threadIdx.x % LOBPCG_WAVE, wave = threadIdx.x / LOBPCG_WAVE;
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        T v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        const int q = threadIdx.x;
+        T v = red[0][q];
+        for (int w = 1; w < HEAVY_THREADS / LOBPCG_WAVE; ++w) v += red[w][q];
+        Y[i * k + q] = v + diag[i] * X[i * k + q];
+    }
+}
+
 #ifndef LOBPCG_TW_LDS
 #define LOBPCG_TW_LDS 0         // bytes of LDS for staged X blocks per workgroup (0: by block width)
 #endif
@@ -393,6 +431,17 @@ void spmm_pull_launch(lobpcg_ctx *ctx, const T *X, T *Y, int k, hipStream_t s) {
     else
         spmm_pull_kernel<T, 16, TILED><<<grid, SPMM_THREADS, 0, s>>>(SPMM_ARGS);
 #undef SPMM_ARGS
+    if (!TILED && ctx->n_heavy > 0) {
+        const int hg = (int)ctx->n_heavy;
+#define HEAVY_ARGS k, ctx->heavy_rows, ctx->rp, ctx->ci, rv, ctx->cp, ctx->cri, cv, diag, X, Y
+        if (k <= 4)
+            spmm_heavy_kernel<T, 4><<<hg, HEAVY_THREADS, 0, s>>>(HEAVY_ARGS);
+        else if (k <= 8)
+            spmm_heavy_kernel<T, 8><<<hg, HEAVY_THREADS, 0, s>>>(HEAVY_ARGS);
+        else
+            spmm_heavy_kernel<T, 16><<<hg, HEAVY_THREADS, 0, s>>>(HEAVY_ARGS);
+#undef HEAVY_ARGS
+    }
 }
 
 template <typename T>
@@ -481,6 +530,16 @@ int build_csc(lobpcg_ctx *ctx, hipStream_t s) {
     if (m) {
         HIP_TRY(ctx, hipMemcpyAsync(ctx->cri, ri.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipMemcpyAsync(ctx->cval, cv.data(), m * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    // long rows for spmm_heavy_kernel
+    std::vector<int32_t> heavy;
+    for (int64_t i = 0; i < n; ++i)
+        if ((rp[i + 1] - rp[i]) + (cp[i + 1] - cp[i]) > HEAVY_ROW) heavy.push_back((int32_t)i);
+    ctx->n_heavy = (int64_t)heavy.size();
+    if (!heavy.empty()) {
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->heavy_rows, heavy.size() * sizeof(int32_t)));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->heavy_rows, heavy.data(), heavy.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s));
     }
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (ctx->format_request == LOBPCG_FORMAT_CSR) return LOBPCG_OK;

@@ -15,9 +15,11 @@ from gpu_util import row_error, torch_cuda, to_dev, upload
 pytestmark = pytest.mark.gpu
 
 
-def int_matrix(n, draws, seed, vmax=4):
-    """random_sym pattern with small integer values (exact in FP32 and BF16)."""
-    A = synth.random_sym(n, draws, seed=seed, f32=False)
+def int_matrix(n, draws, seed, vmax=4, hubs=False):
+    """random_sym (or power-law, with rows longer than the CSR kernel's
+    one-workgroup threshold) pattern with small integer values (exact in FP32
+    and BF16)."""
+    A = synth.zipf(n, lmin=4, lmax=6000, seed=seed) if hubs else synth.random_sym(n, draws, seed=seed, f32=False)
     rng = np.random.default_rng(seed)
     v = rng.integers(-vmax, vmax + 1, size=A.nnz).astype(np.float64)
     v[v == 0] = 1.0
@@ -31,6 +33,8 @@ MATRICES = {
     "tiled": lambda: synth.tiled(64 * 40, tile=64, tile_draws=5, p=0.1, seed=2),
     "zipf": lambda: synth.zipf(4000, lmin=4, lmax=400, seed=5),
     "tiny": lambda: synth.random_sym(7, 3, seed=1),
+    # power-law rows: ~270 of them longer than 1024 entries (the CSR long-row kernel)
+    "hubs": lambda: synth.zipf(20000, lmin=4, lmax=6000, seed=7),
 }
 
 
@@ -55,10 +59,11 @@ def test_spmm_parity(name, k, f32, fmt):
 
 @pytest.mark.parametrize("k", [1, 8, 16])
 @pytest.mark.parametrize("fmt", ["csr", "tiled"])
-def test_spmm_integer_bitwise(k, fmt):
+@pytest.mark.parametrize("hubs", [False, True])
+def test_spmm_integer_bitwise(k, fmt, hubs):
     import paper_2109_00485_amd as L
     torch = torch_cuda()
-    A = int_matrix(2000, 25, seed=4)
+    A = int_matrix(20000 if hubs else 2000, 25, seed=4, hubs=hubs)
     ctx = upload(A, True, fmt={"csr": L.FORMAT_CSR, "tiled": L.FORMAT_TILED}[fmt])
     X = np.random.default_rng(0).integers(-8, 9, size=(A.n, k)).astype(np.float32)
     Y = ctx.spmm_sym(to_dev(X, np.float32)).cpu().numpy()
