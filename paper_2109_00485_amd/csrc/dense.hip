@@ -6,7 +6,7 @@
 //    lower blocks of eq. Glower, scale both by diag(O)^{-1/2} (equivalent to
 //    normalising the columns of S), Cholesky O = L L^T, A = L^{-1} G L^{-T},
 //    cyclic Jacobi with a round-robin pairing (all N/2 rotations of a round
-//    are disjoint and applied at once), sort ascending, C = diag(O)^{-1/2}
+//    are disjoint and applied at once, in place, by 2 x 2 blocks), sort ascending, C = diag(O)^{-1/2}
 //    L^{-T} V[:, :k].  If O is not positive definite with P, P is dropped
 //    and the step repeated with S = [X, W].
 #include <cfloat>
@@ -104,10 +104,19 @@ __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__rest
 
 // Rayleigh-Ritz.  M is the Gram output [X W P]^T [X W P HX HW HP] for nblk_in
 // blocks (KA = nblk_in*k rows, KB = 2*KA columns).  One workgroup of
-// RR_THREADS threads; every thread owns a fixed set of matrix entries for the
-// Jacobi rounds.
+// RR_THREADS threads.
+//
+// Jacobi rounds update in place by 2 x 2 blocks: a round pairs the indices
+// into disjoint pairs (p_a, q_a); the entries of A with rows in pair a and
+// columns in pair b depend only on each other (A' = J_a^T A[a, b] J_b), so
+// one thread reads, rotates and writes one block and its mirror (a <= b only,
+// which keeps A exactly symmetric), and one thread rotates one row of V for
+// one pair (V' = V J).  Every thread derives the pairs of a round from the
+// round number, so its loads of A, V and of the rotations are independent.
 constexpr int RR_THREADS = 256;
-constexpr int RQ = (NMAX * NMAX + RR_THREADS - 1) / RR_THREADS;
+constexpr int NPAIR = NMAX / 2;
+constexpr int RR_BLK = (NPAIR * (NPAIR + 1) / 2 + RR_THREADS - 1) / RR_THREADS;   // blocks per thread
+constexpr int RR_VROW = (NMAX * NPAIR + RR_THREADS - 1) / RR_THREADS;            // V items per thread
 
 __device__ inline double block_total(double v, double *sh) {
     v = wave_sum(v);
@@ -120,19 +129,34 @@ __device__ inline double block_total(double v, double *sh) {
     return t;
 }
 
+// Pair a of round r of the round-robin ordering over Ne (even) indices:
+// position 0 stays, the others rotate; returns p < q (q = Ne - 1 may be a
+// dummy index when the order is odd).
+__device__ inline void rr_pair(int a, int r, int Ne, int &p, int &q) {
+    int x = 0;
+    if (a > 0) {
+        x = a - 1 + r;
+        if (x >= Ne - 1) x -= Ne - 1;
+        x += 1;
+    }
+    int y = Ne - 2 - a + r;
+    if (y >= Ne - 1) y -= Ne - 1;
+    y += 1;
+    p = x < y ? x : y;
+    q = x < y ? y : x;
+}
+
 __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, const double *__restrict__ M,
                                                         double *__restrict__ Cout, double *__restrict__ theta,
                                                         int *__restrict__ flags, double tol) {
     __shared__ double O[NMAX * LD];
-    __shared__ double Abuf[2][NMAX * LD];   // Jacobi rounds alternate between two copies
-    __shared__ double Vbuf[2][NMAX * LD];
+    __shared__ double A[NMAX * LD];
+    __shared__ double V[NMAX * LD];
     __shared__ double sc[NMAX];
     __shared__ int idx[NMAX];
-    __shared__ double rot_c[NMAX], rot_s[NMAX];
-    __shared__ int partner[NMAX];
+    __shared__ double pr_c[NPAIR], pr_s[NPAIR];
     __shared__ double sh[RR_THREADS / LOBPCG_WAVE];
     __shared__ double Ys[NMAX * KM_CHOL];
-    double *A = Abuf[0], *V = Vbuf[0];
     const int t = threadIdx.x;
     if (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL)) return;
     const int KA = nblk_in * k, KB = 2 * KA;
@@ -199,97 +223,142 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
             }
         }
         __syncthreads();
-        // this thread's entries (fixed for the whole Jacobi iteration)
-        int ei[RQ], ej[RQ];
-#pragma unroll
-        for (int q = 0; q < RQ; ++q) {
-            const int e = t + RR_THREADS * q;
-            ei[q] = e < N * N ? e / N : -1;
-            ej[q] = e < N * N ? e % N : 0;
-        }
-        // symmetrise, V = I
-        double ra[RQ];
-#pragma unroll
-        for (int q = 0; q < RQ; ++q)
-            if (ei[q] >= 0) ra[q] = 0.5 * (A[ei[q] * LD + ej[q]] + A[ej[q] * LD + ei[q]]);
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < RQ; ++q)
-            if (ei[q] >= 0) {
-                A[ei[q] * LD + ej[q]] = ra[q];
-                V[ei[q] * LD + ej[q]] = ei[q] == ej[q] ? 1.0 : 0.0;
+        // symmetrise (both triangles from their average), V = I
+        for (int e = t; e < N * N; e += RR_THREADS) {
+            const int i = e / N, j = e % N;
+            const double v = i == j ? A[i * LD + j] : 0.5 * (A[i * LD + j] + A[j * LD + i]);
+            V[i * LD + j] = i == j ? 1.0 : 0.0;
+            if (i >= j) {
+                A[i * LD + j] = v;
+                A[j * LD + i] = v;
             }
+        }
         __syncthreads();
-        // cyclic Jacobi, round-robin pairing over Ne = N rounded up to even:
-        // all Ne/2 rotations of a round are disjoint and applied at once as
-        // A <- J^T A J, V <- V J, with J acting on index i as
-        // (new)_i = c_i (old)_i + s_i (old)_partner(i)
-        const int Ne = N + (N & 1);
+        // cyclic Jacobi, round-robin pairing over Ne = N rounded up to even
+        // (index N, if present, is a dummy whose rotation is the identity)
+        const int Ne = N + (N & 1), NP = Ne / 2, NB = NP * (NP + 1) / 2;
+        // this thread's blocks (a <= b) and V items (row, pair), fixed for all rounds
+        int ba[RR_BLK], bb[RR_BLK], vi[RR_VROW], vb[RR_VROW];
+#pragma unroll
+        for (int m = 0; m < RR_BLK; ++m) {
+            const int e = t + RR_THREADS * m;
+            int a = 0, rem = e;
+            while (rem >= NP - a && a < NP) {
+                rem -= NP - a;
+                ++a;
+            }
+            ba[m] = e < NB ? a : -1;
+            bb[m] = a + rem;
+        }
+#pragma unroll
+        for (int m = 0; m < RR_VROW; ++m) {
+            const int e = t + RR_THREADS * m;
+            vi[m] = e < N * NP ? e / NP : -1;
+            vb[m] = e % NP;
+        }
         for (int sweep = 0; sweep < 30; ++sweep) {
             double off = 0.0, tot = 0.0;
-#pragma unroll
-            for (int q = 0; q < RQ; ++q)
-                if (ei[q] >= 0) {
-                    const double v = A[ei[q] * LD + ej[q]];
-                    tot += v * v;
-                    if (ei[q] != ej[q]) off += v * v;
-                }
+            for (int e = t; e < N * N; e += RR_THREADS) {
+                const int i = e / N, j = e % N;
+                const double v = A[i * LD + j];
+                tot += v * v;
+                if (i != j) off += v * v;
+            }
             off = block_total(off, sh);
             tot = block_total(tot, sh);
             // stop at an off-diagonal norm of 1e-13 of the matrix norm: below that the
             // rounding of the two-sided updates keeps it from shrinking further
             if (off <= 1e-26 * tot || off == 0.0) break;
             for (int r = 0; r < Ne - 1; ++r) {
-                if (t < Ne / 2) {
-                    const int pos_p = t, pos_q = Ne - 1 - t;
-                    int p = pos_p == 0 ? 0 : 1 + (pos_p - 1 + r) % (Ne - 1);
-                    int q = 1 + (pos_q - 1 + r) % (Ne - 1);
-                    if (p > q) { int tmp = p; p = q; q = tmp; }
+                if (t < NP) {
+                    int p, q;
+                    rr_pair(t, r, Ne, p, q);
+                    // tan of the angle that annihilates a_pq: the root of smaller
+                    // magnitude of t^2 + 2 t (a_qq - a_pp) / (2 a_pq) - 1 = 0
+                    double c = 1.0, sn = 0.0;
                     if (q < N) {
-                        double c = 1.0, sn = 0.0;
-                        const double apq = A[p * LD + q];
-                        if (apq != 0.0) {
-                            const double tau = (A[q * LD + q] - A[p * LD + p]) / (2.0 * apq);
-                            const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        const double g2 = 2.0 * A[p * LD + q];
+                        const double h = A[q * LD + q] - A[p * LD + p];
+                        const double rad = sqrt(h * h + g2 * g2);
+                        if (g2 != 0.0 && rad > 0.0) {   // rad = 0: both below the square's range, no rotation
+                            const double tt = (h >= 0 ? g2 : -g2) / (fabs(h) + rad);
                             c = 1.0 / sqrt(1.0 + tt * tt);
                             sn = tt * c;
                         }
-                        partner[p] = q; partner[q] = p;
-                        rot_c[p] = c; rot_s[p] = -sn;
-                        rot_c[q] = c; rot_s[q] = sn;
-                    } else if (p < N) {
-                        partner[p] = p; rot_c[p] = 1.0; rot_s[p] = 0.0;
                     }
+                    pr_c[t] = c;
+                    pr_s[t] = sn;
                 }
                 __syncthreads();
-                // read the current copies, write the other ones (no write-back pass)
-                double *An = (A == Abuf[0]) ? Abuf[1] : Abuf[0];
-                double *Vn = (V == Vbuf[0]) ? Vbuf[1] : Vbuf[0];
+                // A <- J^T A J by blocks: new column p = c p - s q, new column q = s p + c q
 #pragma unroll
-                for (int q = 0; q < RQ; ++q) {
-                    if (ei[q] >= 0) {
-                        const int i = ei[q], j = ej[q];
-                        const int pi = partner[i], pj = partner[j];
-                        const double ci = rot_c[i], si = rot_s[i], cj = rot_c[j], sj = rot_s[j];
-                        An[i * LD + j] = ci * (cj * A[i * LD + j] + sj * A[i * LD + pj]) +
-                                         si * (cj * A[pi * LD + j] + sj * A[pi * LD + pj]);
-                        Vn[i * LD + j] = cj * V[i * LD + j] + sj * V[i * LD + pj];
+                for (int m = 0; m < RR_BLK; ++m) {
+                    if (ba[m] < 0) continue;
+                    const int a = ba[m], b = bb[m];
+                    int p1, q1, p2, q2;
+                    rr_pair(a, r, Ne, p1, q1);
+                    rr_pair(b, r, Ne, p2, q2);
+                    const bool v1 = q1 < N, v2 = q2 < N;
+                    const double c1 = pr_c[a], s1 = pr_s[a], c2 = pr_c[b], s2 = pr_s[b];
+                    const double x11 = A[p1 * LD + p2];
+                    const double x12 = v2 ? A[p1 * LD + q2] : 0.0;
+                    const double x21 = v1 ? A[q1 * LD + p2] : 0.0;
+                    const double x22 = v1 && v2 ? A[q1 * LD + q2] : 0.0;
+                    const double y11 = c2 * x11 - s2 * x12, y12 = s2 * x11 + c2 * x12;
+                    const double y21 = c2 * x21 - s2 * x22, y22 = s2 * x21 + c2 * x22;
+                    const double z11 = c1 * y11 - s1 * y21, z21 = s1 * y11 + c1 * y21;
+                    const double z12 = c1 * y12 - s1 * y22, z22 = s1 * y12 + c1 * y22;
+                    if (a == b) {
+                        // the rotated pair: its off-diagonal entry is annihilated
+                        A[p1 * LD + p1] = z11;
+                        if (v1) {
+                            A[q1 * LD + q1] = z22;
+                            A[p1 * LD + q1] = 0.0;
+                            A[q1 * LD + p1] = 0.0;
+                        }
+                    } else {
+                        A[p1 * LD + p2] = z11;
+                        A[p2 * LD + p1] = z11;
+                        if (v2) {
+                            A[p1 * LD + q2] = z12;
+                            A[q2 * LD + p1] = z12;
+                        }
+                        if (v1) {
+                            A[q1 * LD + p2] = z21;
+                            A[p2 * LD + q1] = z21;
+                        }
+                        if (v1 && v2) {
+                            A[q1 * LD + q2] = z22;
+                            A[q2 * LD + q1] = z22;
+                        }
                     }
                 }
-                A = An;
-                V = Vn;
+                // V <- V J, one (row, pair) per item
+#pragma unroll
+                for (int m = 0; m < RR_VROW; ++m) {
+                    if (vi[m] < 0) continue;
+                    const int i = vi[m], b = vb[m];
+                    int p, q;
+                    rr_pair(b, r, Ne, p, q);
+                    if (q < N) {
+                        const double c = pr_c[b], sn = pr_s[b];
+                        const double vp = V[i * LD + p], vq = V[i * LD + q];
+                        V[i * LD + p] = c * vp - sn * vq;
+                        V[i * LD + q] = sn * vp + c * vq;
+                    }
+                }
                 __syncthreads();
             }
         }
         // ascending order (ties by index)
-        if (t < N) {
-            double li = A[t * LD + t];
+        for (int i0 = t; i0 < N; i0 += RR_THREADS) {
+            double li = A[i0 * LD + i0];
             int rank = 0;
             for (int j = 0; j < N; ++j) {
                 double lj = A[j * LD + j];
-                rank += (lj < li) || (lj == li && j < t);
+                rank += (lj < li) || (lj == li && j < i0);
             }
-            idx[rank] = t;
+            idx[rank] = i0;
         }
         __syncthreads();
         // C = diag(sc) L^{-T} V[:, idx[0..k)]

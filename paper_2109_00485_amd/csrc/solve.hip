@@ -8,7 +8,7 @@
 //   G, O from the lower blocks of [X W P]^T [X W P HX HW HP]   (eq. Glower)
 //   Rayleigh-Ritz on (G, O) -> C, Theta             (eq. rreig)
 //   X, HX, P, HP <- [X W P] C, [HX HW HP] C, ...    (eqs. xupd, pupd, upd1-upd2)
-//   R = HX - X Theta, column norms, W = K^{-1} R    (lines 10 and 6)
+//   R = HX - X Theta, column norms, W = K^{-1} R    (Algorithm 1: residual, preconditioner)
 // Convergence: rel_j = ||r_j|| / (max(|theta_j|, tau) ||x_j||) <= tol for the
 // nev wanted columns; then H X is recomputed explicitly, theta_j becomes the
 // Rayleigh quotient x_j^T H x_j / x_j^T x_j, and the test is repeated.
@@ -106,7 +106,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     HIP_TRY(ctx, hipMemcpyAsync(ctx->X, Xuser, blk, hipMemcpyDeviceToDevice, s));
     TRY(launch_set_flags(ctx, 0, 0, s));
     tm.mark(0);
-    // Algorithm 1, lines 1-4: Rayleigh-Ritz on X0
+    // Algorithm 1, start: Rayleigh-Ritz on X0
     TRY(launch_spmm(ctx, ctx->X, ctx->HX, k, s));
     ++n_spmm;
     tm.mark(1);

@@ -83,6 +83,39 @@ def test_random_sym_20k(f32):
     assert r.confirmations >= 1
 
 
+@pytest.mark.parametrize("k,nev", [(3, 2), (5, 3), (16, 5)])
+def test_block_sizes_against_dense_spectrum(k, nev):
+    """Odd and largest Rayleigh-Ritz pencils (3k = 9, 15 and 48; an odd order
+    leaves one index unpaired in every Jacobi round), FP64, against the
+    spectrum of the dense matrix."""
+    A = W.make_matrix("random_sym_1k")
+    H = oracle.SymMatrix.from_csr(A)
+    lam = np.linalg.eigvalsh(H @ np.eye(A.n))[:nev]
+    ctx, r, Xg = gpu_solve(A, False, k=k, nev=nev, maxiter=5000)
+    assert r.status == 0, r
+    tau = 1e-3 * H.gershgorin()
+    assert np.all(np.abs(r.evals[:nev] - lam) <= 1e-6 * np.maximum(np.abs(lam), tau)), (r.evals[:nev], lam)
+    assert np.abs(Xg.T @ Xg - np.eye(k)).max() < 1e-10
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_precond_offset_solve(f32):
+    """Shift two Ritz-value spreads below theta_j: the same eigenpairs as the
+    oracle run with the same shift, in about as many iterations (FP64 follows
+    the oracle's steps; rounding differences change the count slightly)."""
+    A = W.make_matrix("random_sym_20k")
+    H, ref = oracle_solve("rs20k", A, precond_offset=2.0)
+    import paper_2109_00485_amd as L
+    ctx = upload(A, f32)
+    ctx.set_precond_offset(2.0)
+    dt = np.float32 if f32 else np.float64
+    X = to_dev(W.initial_block(A.n, 8, seed=1), dt)
+    r = ctx.solve(X, 5, maxiter=5000)
+    assert r.status == 0, r
+    check_against_oracle(H, ref, r, X.cpu().numpy().astype(np.float64), f32)
+    assert abs(r.iters - ref.iters) <= max(5, 0.1 * ref.iters), (r.iters, ref.iters)
+
+
 def test_bf16x3_gram_solve():
     """Split-BF16 Gram products (about 2^-18 relative error per product) put a
     residual floor near 1e-5..1e-4 under the solve; the eigenvalues still meet
