@@ -130,18 +130,33 @@ void lobpcg_destroy(lobpcg_ctx *ctx);
 int lobpcg_spmm_sym(lobpcg_ctx *ctx, const void *X, void *Y, int k, void *stream);
 
 /*
- * lobpcg_precond_apply -- W = K^{-1} R, Algorithm 1 line 6.  With
- * LOBPCG_PRECOND_DIAG, K is the diagonal of H shifted per column by the Ritz
- * value theta_j (the 1x1-tile case of the block-diagonal preconditioner of
- * Section 3.4): W_ij = R_ij / s(d_i - theta_j), s(x) = x if |x| >= eps else
- * +-eps (sign of x, + for 0), eps = eps_rel * gamma.  With LOBPCG_PRECOND_MLP
- * the attached network supplies the scaling (lobpcg_set_mlp).
+ * lobpcg_precond_apply -- W = K^{-1} R, the preconditioning step of
+ * Algorithm 1.  With LOBPCG_PRECOND_DIAG, K is the diagonal of H shifted per
+ * column (the 1x1-tile case of the block-diagonal preconditioner of Section
+ * 3.4, whose shift lies near an approximate wanted eigenvalue):
+ * W_ij = R_ij / s(d_i - sigma_j), sigma_j = theta_j - c (max theta - min theta)
+ * with c the context's offset (lobpcg_set_precond_offset; default 0, i.e. the
+ * shift is the Ritz value theta_j itself), s(x) = x if |x| >= eps else +-eps
+ * (sign of x, + for 0), eps = eps_rel * gamma.  With LOBPCG_PRECOND_MLP the
+ * attached network supplies a factor on that step (lobpcg_set_mlp).
  *   R      device, n x k row-major
  *   theta  device, double[k]
  *   W      device, n x k row-major, written (may alias R)
  */
 int lobpcg_precond_apply(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k,
                          int kind, void *stream);
+
+/*
+ * lobpcg_set_precond_offset -- place the diagonal preconditioner's shift c
+ * Ritz-value spreads below each Ritz value: sigma_j = theta_j - c (max theta -
+ * min theta) over the k values of the block (Section 3.4 puts the shift near
+ * an approximate wanted eigenvalue).  Applies to lobpcg_precond_apply, to the
+ * preconditioner inside lobpcg_solve, to the diagonal step the learned
+ * preconditioner scales, and to harvested training samples.  c = 0 (the
+ * default) is the shift at theta_j.  Returns LOBPCG_EINVAL unless
+ * 0 <= c <= 1e6.  Host-only; takes effect on the next launch.
+ */
+int lobpcg_set_precond_offset(lobpcg_ctx *ctx, double c);
 
 /*
  * lobpcg_gram -- G = A^T B for tall-skinny blocks (the products that form the

@@ -3,7 +3,8 @@
 For a block X (n x k) with H X, Ritz values theta and converged eigenvectors
 x* (n x nev) of the same matrix, column j yields one group:
     E_j  = x*_j - X (X^T x*_j)        the exact correction outside span(X)
-    R_ij = (H X)_ij - theta_j X_ij,   U_ij = R_ij / s(d_i - theta_j)
+    R_ij = (H X)_ij - theta_j X_ij,   U_ij = R_ij / s(d_i - sigma_j)
+    (sigma_j the diagonal preconditioner's shift, theta_j unless an offset is given)
     p_i  = min(1, rows (1/(2n) + |E_ij| / (2 sum_l |E_lj|)))
 and row i is kept when u(seed, group, i) < p_i, with weight 1/p_i.  The
 uniform draw u is SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): with
@@ -44,7 +45,7 @@ def uniform(seed: int, group: int, i) -> np.ndarray:
     return (r >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
 
 
-def harvest_block(X, HX, theta, xstar, d, rownorm, tilemean, eps, rows, nev, seed, group0):
+def harvest_block(X, HX, theta, xstar, d, rownorm, tilemean, eps, rows, nev, seed, group0, offset=0.0):
     """Per column j < nev: dict of kept rows and their sample fields (in row order)."""
     X = np.asarray(X, dtype=np.float64)
     HX = np.asarray(HX, dtype=np.float64)
@@ -62,7 +63,8 @@ def harvest_block(X, HX, theta, xstar, d, rownorm, tilemean, eps, rows, nev, see
         u = uniform(seed, group0 + j, np.arange(n))
         keep = np.nonzero(u < p)[0]
         R = HX[:, j] - X[:, j] * theta[j]
-        U = R / guard(d - theta[j], eps)
+        sigma_j = theta[j] - offset * (theta.max() - theta.min())
+        U = R / guard(d - sigma_j, eps)
         out.append(dict(row=keep, p=p[keep], u=u[keep], p_all=p, u_all=u, E=E[keep], U=U[keep], w=1.0 / p[keep],
                         feat=np.stack([d[keep], np.full(keep.size, theta[j]), np.asarray(rownorm)[keep],
                                        np.asarray(tilemean)[keep]], axis=1),

@@ -70,22 +70,23 @@ def rel_residuals(R: np.ndarray, X: np.ndarray, theta: np.ndarray, tau: float) -
 def lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: int = 5000,
            precond: Optional[Callable] = "diag", d: Optional[np.ndarray] = None,
            tau_rel: float = 1e-3, eps_rel: float = 1e-5,
-           callback: Optional[Callable] = None) -> Result:
+           callback: Optional[Callable] = None, precond_offset: float = 0.0) -> Result:
     """See :func:`_lobpcg`.  Small problems run the dense BLAS single-threaded
     (thread start-up dominates there); the arithmetic is unchanged."""
     if X0.shape[0] < 200_000:
         with threadpool_limits(1, user_api="blas"):
-            return _lobpcg(H, X0, nev, tol, maxiter, precond, d, tau_rel, eps_rel, callback)
-    return _lobpcg(H, X0, nev, tol, maxiter, precond, d, tau_rel, eps_rel, callback)
+            return _lobpcg(H, X0, nev, tol, maxiter, precond, d, tau_rel, eps_rel, callback, precond_offset)
+    return _lobpcg(H, X0, nev, tol, maxiter, precond, d, tau_rel, eps_rel, callback, precond_offset)
 
 
 def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: int = 5000,
             precond: Optional[Callable] = "diag", d: Optional[np.ndarray] = None,
             tau_rel: float = 1e-3, eps_rel: float = 1e-5,
-            callback: Optional[Callable] = None) -> Result:
+            callback: Optional[Callable] = None, precond_offset: float = 0.0) -> Result:
     """Lowest ``nev`` eigenpairs of H from the starting block X0 (n x k, k >= nev).
 
-    ``precond``: "diag" (needs ``d``, the diagonal of H), None (identity), or a
+    ``precond``: "diag" (needs ``d``, the diagonal of H; its shift lies
+    ``precond_offset`` Ritz-value spreads below theta_j), None (identity), or a
     callable ``f(R, theta, X) -> W``.  ``callback(it, X, R, theta, W)`` is called
     each iteration before the Rayleigh-Ritz step (used to harvest training data).
     """
@@ -102,7 +103,7 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
         dd = np.asarray(d, dtype=np.float64)
 
         def apply_k(R, theta, X):
-            return diag_precond(R, dd, theta, eps)
+            return diag_precond(R, dd, theta, eps, precond_offset)
     elif precond is None:
         def apply_k(R, theta, X):
             return R.copy()
@@ -110,7 +111,7 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
         apply_k = precond
 
     n_spmm = 0
-    # Algorithm 1, lines 1-4: Rayleigh-Ritz on X0
+    # Algorithm 1, start: Rayleigh-Ritz on X0
     HX0 = H @ X0
     n_spmm += 1
     G, O = assemble_pencil([X0], [HX0])
@@ -138,7 +139,7 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
         if it >= maxiter:
             break
         it += 1
-        # line 6: W = K^{-1} R
+        # preconditioned residual W = K^{-1} R
         W = np.asarray(apply_k(R, theta, X), dtype=np.float64)
         if callback is not None:
             callback(it, X, R, theta, W)
@@ -156,7 +157,7 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
                 break
         HW = H @ W
         n_spmm += 1
-        # lines 7-8: Rayleigh-Ritz on S = [X, W, P]
+        # Rayleigh-Ritz on S = [X, W, P] (eq. rreig)
         if P is not None:
             S, HS = [X, W, P], [HX, HW, HP]
         else:
@@ -176,7 +177,7 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
             except NotSPD:
                 res.status = ENOTSPD
                 break
-        # lines 9-11 with the recurrences eqs. upd1-upd2
+        # update of X, P and their products with the recurrences eqs. upd1-upd2
         Sm = np.hstack(S)
         HSm = np.hstack(HS)
         X = Sm @ C

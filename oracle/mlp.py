@@ -116,8 +116,11 @@ def guard(x, eps):
     return np.where(np.abs(x) >= eps, x, np.where(x < 0, -eps, eps))
 
 
-def precond_scale(p: Params, d, theta, rownorm, tilemean, eps, a1_f32: bool = False) -> np.ndarray:
-    """m_ij (n x k) for every row i and Ritz value theta_j; non-finite -> diagonal."""
+def precond_scale(p: Params, d, theta, rownorm, tilemean, eps, a1_f32: bool = False,
+                  offset: float = 0.0) -> np.ndarray:
+    """m_ij (n x k) for every row i and Ritz value theta_j; non-finite -> diagonal.
+    The diagonal step divides by s(d_i - sigma_j), sigma_j = theta_j - offset *
+    (max theta - min theta) (offset 0: the Ritz value itself)."""
     d = np.asarray(d, dtype=np.float64)
     theta = np.asarray(theta, dtype=np.float64)
     n, k = d.size, theta.size
@@ -128,7 +131,8 @@ def precond_scale(p: Params, d, theta, rownorm, tilemean, eps, a1_f32: bool = Fa
     f[:, :, 3] = np.asarray(tilemean, dtype=np.float64)[:, None]
     o, _ = forward(p, standardize(p, f.reshape(-1, NIN)), a1_f32=a1_f32)
     o = o.reshape(n, k)
-    base = 1.0 / guard(d[:, None] - theta[None, :], eps)
+    sigma = theta - offset * (theta.max() - theta.min())
+    base = 1.0 / guard(d[:, None] - sigma[None, :], eps)
     m = np.exp(bound(o)) * base
     return np.where(np.isfinite(m), m, base)
 

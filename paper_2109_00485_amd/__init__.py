@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_mlp_last_error.argtypes = [P]
     lib.lobpcg_set_mlp.restype = cint
     lib.lobpcg_set_mlp.argtypes = [P, P]
+    lib.lobpcg_set_precond_offset.restype = cint
+    lib.lobpcg_set_precond_offset.argtypes = [P, dbl]
     lib.lobpcg_get_features.restype = cint
     lib.lobpcg_get_features.argtypes = [P, P, P, P]
     lib.lobpcg_mlp_forward.restype = cint
@@ -198,6 +200,7 @@ class Context:
         self.dtype = dtype
         self.torch_dtype = tval
         self.kmax = kmax
+        self.precond_offset = 0.0
 
     @classmethod
     def from_csr(cls, A, device="cuda", **kw):
@@ -270,6 +273,11 @@ class Context:
                                        _dev_ptr(B, self.torch_dtype, "B"), kb,
                                        _dev_ptr(G, torch.float64, "G"), prec, _stream_ptr(stream)), "gram")
         return G
+
+    def set_precond_offset(self, c: float):
+        """Diagonal preconditioner shift sigma_j = theta_j - c (theta_max - theta_min); 0 = theta_j."""
+        self._check(load().lobpcg_set_precond_offset(self._h, float(c)), "set_precond_offset")
+        self.precond_offset = float(c)
 
     def set_mlp(self, mlp):
         """Attach a network for PRECOND_MLP (None detaches); keep it alive while attached."""

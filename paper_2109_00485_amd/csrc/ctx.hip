@@ -203,6 +203,13 @@ extern "C" const char *lobpcg_strerror(int status) {
 
 extern "C" const char *lobpcg_last_error(const lobpcg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+extern "C" int lobpcg_set_precond_offset(lobpcg_ctx *ctx, double c) {
+    if (!ctx) return LOBPCG_EINVAL;
+    if (!(c >= 0.0) || !(c <= 1e6)) return set_err(ctx, LOBPCG_EINVAL, "precond offset %g outside [0, 1e6]", c);
+    ctx->precond_offset = c;
+    return LOBPCG_OK;
+}
+
 extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr, const int32_t *col,
                              const void *val, const lobpcg_opts *opts_in, void *stream) {
     if (!out) return LOBPCG_EINVAL;

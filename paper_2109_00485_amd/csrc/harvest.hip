@@ -93,7 +93,8 @@ template <typename T>
 __global__ __launch_bounds__(HV_THREADS) void select_kernel(
     int64_t n, int k, int nev, int j, const T *__restrict__ X, const T *__restrict__ HX, const T *__restrict__ xs,
     const double *__restrict__ C, const double *__restrict__ sums, const double *__restrict__ theta,
-    const T *__restrict__ d, const float *__restrict__ rho, const float *__restrict__ tmean, double eps, int rows,
+    const T *__restrict__ d, const float *__restrict__ rho, const float *__restrict__ tmean, double eps, double off,
+    int rows,
     uint64_t seed, uint64_t group, int64_t capacity, float *__restrict__ feat, float *__restrict__ U,
     float *__restrict__ Tt, float *__restrict__ w, float *__restrict__ Xrow, int32_t *__restrict__ rowid,
     unsigned long long *__restrict__ counter) {
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(HV_THREADS) void select_kernel(
     if (pos >= capacity) return;
     const double th = theta[j];
     const double di = (double)d[i];
-    const double dm = di - th;
+    const double dm = di - th + off * ritz_spread(theta, k);
     const double sg = fabs(dm) >= eps ? dm : (dm < 0 ? -eps : eps);
     const double r = (double)HX[i * k + j] - (double)X[i * k + j] * th;
     feat[pos * 4 + 0] = (float)di;
@@ -159,7 +160,7 @@ int snapshot(lobpcg_ctx *ctx, const void *Xv, const void *HXv, const double *the
         const int gidx = h->ngroups + j;
         select_kernel<T><<<ceil_div(ctx->n, HV_THREADS), HV_THREADS, 0, s>>>(
             ctx->n, k, nev, j, X, HX, xs, ctx->gram_out2, sums, theta, (const T *)ctx->diag, ctx->feat_rownorm,
-            ctx->feat_tilemean, eps, h->rows, h->seed, (uint64_t)gidx, h->capacity, h->feat, h->U, h->T, h->w,
+            ctx->feat_tilemean, eps, ctx->precond_offset, h->rows, h->seed, (uint64_t)gidx, h->capacity, h->feat, h->U, h->T, h->w,
             h->Xrow, h->row, ctx->harvest_counter);
         close_group_kernel<<<1, 1, 0, s>>>(ctx->harvest_counter, h->group_off, gidx);
     }

@@ -12,6 +12,17 @@
 #define LOBPCG_WAVE 64
 #define HEAVY_ROW 1024
 
+// Spread max_j theta_j - min_j theta_j of the k Ritz values: the diagonal
+// preconditioner's shift is sigma_j = theta_j - precond_offset * spread.
+__device__ inline double ritz_spread(const double *theta, int k) {
+    double lo = theta[0], hi = theta[0];
+    for (int j = 1; j < k; ++j) {
+        lo = fmin(lo, theta[j]);
+        hi = fmax(hi, theta[j]);
+    }
+    return hi - lo;
+}
+
 // Device-side error flags raised by validation and by the dense kernels.
 enum : int {
     FLAG_BAD_ROWPTR = 1,
@@ -74,6 +85,8 @@ struct lobpcg_ctx {
     int dtype = LOBPCG_F32, format = LOBPCG_FORMAT_CSR, format_request = LOBPCG_FORMAT_AUTO, tile = 64, kmax = 16, gram = LOBPCG_GRAM_AUTO;
     size_t esz = 4;
     double tau_rel = 1e-3, eps_rel = 1e-5, gamma = 0.0;
+    // diagonal preconditioner shift sigma_j = theta_j - precond_offset * (max theta - min theta)
+    double precond_offset = 0.0;
     int refresh_every = 0;  // explicit H X, H P recomputation period (0 = only on apparent convergence)
     int device = 0;
     // strict upper triangle in CSR + diagonal

@@ -123,7 +123,8 @@ __device__ inline float mlp_step(const LaneWeights &L, float z) {
 // trained network reweights the diagonal step by a factor in [e^-2, e^2].
 constexpr float OUT_BOUND = 2.0f;
 
-// W = m o R with m_ij = exp(b(o_ij)) / s(d_i - theta_j); R may alias W.
+// W = m o R with m_ij = exp(b(o_ij)) / s(d_i - sigma_j), sigma_j the diagonal
+// preconditioner's shift of column j; R may alias W.
 // KP > 0 fixes k at compile time (the sample -> (row, column) split is a shift).
 // The next step's inputs are loaded before this step's matrix-core work, so
 // every wave keeps one step of loads in flight.
@@ -133,11 +134,12 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int
                                                                   const float *__restrict__ rho,
                                                                   const float *__restrict__ tmean,
                                                                   const double *__restrict__ theta, const T *R, T *W,
-                                                                  double eps) {
+                                                                  double eps, double off) {
     const int lane = threadIdx.x % LOBPCG_WAVE, c = lane % 16, g = lane / 16;
     const int k = KP ? KP : k_rt;
     LaneWeights L;
     load_lane_weights(L, P, c, g);
+    const double lift = off * ritz_spread(theta, k);   // theta_j - sigma_j of the diagonal step
     const int64_t total = n * k, nsteps = (total + 15) / 16;
     const int64_t wave = ((int64_t)blockIdx.x * INF_THREADS + threadIdx.x) / LOBPCG_WAVE;
     const int64_t nwaves = (int64_t)gridDim.x * (INF_THREADS / LOBPCG_WAVE);
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int
         const float o = mlp_step(L, (float)((cur.f - L.mu) * L.isg));
         const int64_t sidx = st * 16 + c;
         if (g == 0 && sidx < total) {
-            const double dm = cur.f - cur.th;
+            const double dm = cur.f - cur.th + lift;
             const double sg = fabs(dm) >= eps ? dm : (dm < 0 ? -eps : eps);
             const float e = expf(OUT_BOUND * tanhf(o / OUT_BOUND));
             if constexpr (sizeof(T) == 4) {
@@ -641,7 +643,8 @@ int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void
 #define MLP_LAUNCH(T, KP)                                                                                 \
     mlp_precond_kernel<T, KP><<<grid, INF_THREADS, 0, s>>>(ctx->n, k, ctx->mlp->params, (const T *)ctx->diag, \
                                                            ctx->feat_rownorm, ctx->feat_tilemean, theta,     \
-                                                           (const T *)R, (T *)W, eps)
+                                                           (const T *)R, (T *)W, eps,  \
+                                                           ctx->precond_offset)
     if (ctx->dtype == LOBPCG_F32) {
         if (k == 8) MLP_LAUNCH(float, 8);
         else if (k == 16) MLP_LAUNCH(float, 16);

@@ -1,6 +1,6 @@
 // Row-parallel block kernels: the fused LOBPCG update (eqs. xupd, pupd and the
 // recurrences eqs. upd1-upd2), the residual R = H X - X Theta with its column
-// norms (Algorithm 1 line 10), the diagonal preconditioner (line 6), and the
+// norms (the residual step of Algorithm 1), the diagonal preconditioner, and the
 // generic "out = sum_b in_b M_b" combination used by Cholesky QR.
 //
 // One thread owns one row of every block (row-major n x k, so a wavefront
@@ -71,7 +71,7 @@ __device__ inline void mac_cols(T (&acc)[QG], const T (&row)[KM], const T *__res
 template <typename T, int KP>
 __global__ __launch_bounds__(UPD_THREADS) void update_kernel(
     int64_t n, int k_rt, int nblk_host, int nblk_dev, const double *__restrict__ Cg, const double *__restrict__ theta_g,
-    T *X, T *W, T *P, T *HX, T *HW, T *HP, const T *__restrict__ d, int precond, double eps, int write_w,
+    T *X, T *W, T *P, T *HX, T *HW, T *HP, const T *__restrict__ d, int precond, double eps, double off, int write_w,
     double *__restrict__ partial, const int *__restrict__ flags) {
     constexpr int QG = UpdShape<T, KP>::QG;
     if (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL)) return;
@@ -98,6 +98,7 @@ __global__ __launch_bounds__(UPD_THREADS) void update_kernel(
     T thq[QG];
 #pragma unroll
     for (int c = 0; c < QG; ++c) thq[c] = (T)th[q0 + c];
+    const double lift = off * ritz_spread(th, k);   // theta_j - sigma_j
     for (int64_t i0 = (int64_t)blockIdx.x * rpi; i0 < n; i0 += (int64_t)gridDim.x * rpi) {
         const int64_t i = i0 + rr;
         if (!active || i >= n) continue;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(UPD_THREADS) void update_kernel(
             T r = hn[c] - xn[c] * thq[c];
             s_r[c] += (double)r * (double)r;
             s_x[c] += (double)xn[c] * (double)xn[c];
-            wv[c] = precond == LOBPCG_PRECOND_DIAG ? guard_div<T>(r, di - th[q0 + c], eps) : r;
+            wv[c] = precond == LOBPCG_PRECOND_DIAG ? guard_div<T>(r, di - th[q0 + c] + lift, eps) : r;
         }
         // all threads of this row (same wavefront) have read their inputs
         __builtin_amdgcn_wave_barrier();
@@ -169,33 +170,33 @@ __global__ __launch_bounds__(UPD_THREADS) void update_kernel(
 }
 
 // report = {theta, sum r^2, sum x^2, flags, nblk}: the per-workgroup sums
-// reduced in a fixed order (strided over the threads, then a tree)
-constexpr int FIN_THREADS = 256;
+// reduced in a fixed order.  Lane q of a row group reads value q of every
+// FIN_ROWS-th partial row (a wavefront reads two whole rows, coalesced), with
+// eight independent accumulators so that each thread keeps eight loads in
+// flight (the partials were just written by other XCDs: every load is a
+// memory round trip); the row groups are then summed in LDS.
+constexpr int FIN_THREADS = 1024;
+constexpr int FIN_ROWS = FIN_THREADS / (2 * KM);
 __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(int k, int nparts, const double *__restrict__ partial,
                                                                const double *__restrict__ theta,
                                                                const int *__restrict__ flags,
                                                                Report *__restrict__ rep) {
-    __shared__ double red[FIN_THREADS / LOBPCG_WAVE][2 * KM];
-    double acc[2 * KM];
+    __shared__ double red[FIN_ROWS][2 * KM];
+    const int t = threadIdx.x, q0 = t % (2 * KM), g = t / (2 * KM);
+    double a[8];
 #pragma unroll
-    for (int q = 0; q < 2 * KM; ++q) acc[q] = 0.0;
-    for (int p = threadIdx.x; p < nparts; p += FIN_THREADS) {
-        const double *row = partial + (size_t)p * 3 * KM;
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    int p = g;
+    for (; p + 7 * FIN_ROWS < nparts; p += 8 * FIN_ROWS) {
 #pragma unroll
-        for (int q = 0; q < 2 * KM; ++q) acc[q] += row[q];
+        for (int u = 0; u < 8; ++u) a[u] += partial[(size_t)(p + u * FIN_ROWS) * 3 * KM + q0];
     }
-    const int lane = threadIdx.x % LOBPCG_WAVE, wave = threadIdx.x / LOBPCG_WAVE;
-#pragma unroll
-    for (int q = 0; q < 2 * KM; ++q) {
-        double v = acc[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[wave][q] = v;
-    }
+    for (; p < nparts; p += FIN_ROWS) a[0] += partial[(size_t)p * 3 * KM + q0];
+    red[g][q0] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     __syncthreads();
-    const int t = threadIdx.x;
     if (t < 2 * KM) {
         double v = 0.0;
-        for (int w = 0; w < FIN_THREADS / LOBPCG_WAVE; ++w) v += red[w][t];
+        for (int w = 0; w < FIN_ROWS; ++w) v += red[w][t];
         const int s = t / KM, q = t % KM;
         if (q < k) {
             if (s == 0) rep->rnorm2[q] = v; else rep->xnorm2[q] = v;
@@ -256,16 +257,17 @@ template <typename T>
 __global__ __launch_bounds__(UPD_THREADS) void precond_kernel(int64_t n, int k, const T *__restrict__ R,
                                                               const double *__restrict__ theta,
                                                               const T *__restrict__ d, T *__restrict__ W,
-                                                              int kind, double eps) {
+                                                              int kind, double eps, double off) {
     __shared__ double th[KM];
     if (threadIdx.x < k) th[threadIdx.x] = theta[threadIdx.x];
     __syncthreads();
+    const double lift = off * ritz_spread(th, k);
     const int64_t total = n * k;
     for (int64_t e = (int64_t)blockIdx.x * UPD_THREADS + threadIdx.x; e < total; e += (int64_t)gridDim.x * UPD_THREADS) {
         const int64_t i = e / k;
         const int q = (int)(e - i * k);
         T r = R[e];
-        W[e] = kind == LOBPCG_PRECOND_DIAG ? guard_div<T>(r, (double)d[i] - th[q], eps) : r;
+        W[e] = kind == LOBPCG_PRECOND_DIAG ? guard_div<T>(r, (double)d[i] - th[q] + lift, eps) : r;
     }
 }
 
@@ -292,7 +294,7 @@ int launch_update(lobpcg_ctx *ctx, int k, int nblk, int precond, int write_w, hi
 #define UPD_LAUNCH(T, KP)                                                                                        \
     update_kernel<T, KP><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, nblk, nblk > 0, ctx->rr_C, ctx->rr_theta,       \
         (T *)ctx->X, (T *)ctx->W, (T *)ctx->P, (T *)ctx->HX, (T *)ctx->HW, (T *)ctx->HP, (const T *)ctx->diag, pk, \
-        eps, write_w, ctx->norm_partial, ctx->dflags)
+        eps, ctx->precond_offset, write_w, ctx->norm_partial, ctx->dflags)
     if (ctx->dtype == LOBPCG_F32) {
         if (k == 8) UPD_LAUNCH(float, 8);
         else if (k == 16) UPD_LAUNCH(float, 16);
@@ -335,10 +337,12 @@ int launch_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W,
     const double eps = ctx->eps_rel * ctx->gamma;
     if (ctx->dtype == LOBPCG_F32)
         precond_kernel<float><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, (const float *)R, theta,
-                                                           (const float *)ctx->diag, (float *)W, kind, eps);
+                                                           (const float *)ctx->diag, (float *)W, kind, eps,
+                                                           ctx->precond_offset);
     else
         precond_kernel<double><<<grid, UPD_THREADS, 0, s>>>(ctx->n, k, (const double *)R, theta,
-                                                            (const double *)ctx->diag, (double *)W, kind, eps);
+                                                            (const double *)ctx->diag, (double *)W, kind, eps,
+                                                            ctx->precond_offset);
     return LOBPCG_OK;
 }
 

@@ -144,20 +144,23 @@ def test_gram_integer_exact(prec):
     assert np.array_equal(G, a.astype(np.float64).T @ b.astype(np.float64))
 
 
+@pytest.mark.parametrize("offset", [0.0, 2.5])
 @pytest.mark.parametrize("f32", [True, False])
-def test_precond_diag_parity(f32):
+def test_precond_diag_parity(f32, offset):
     import paper_2109_00485_amd as L
     from oracle.precond import diag_precond
     torch = torch_cuda()
     A = synth.random_sym(2000, 10, seed=8, f32=f32)
     dt = np.float32 if f32 else np.float64
     ctx = upload(A, f32)
+    ctx.set_precond_offset(offset)
     gamma = ctx.query()["gamma"]
     R = synth.gaussian_block(A.n, 8, seed=4).astype(dt)
     # shifts chosen so that some d_i - theta_j fall inside the guard band
     theta = np.array([A.diag[0], A.diag[10], -1.0, 5.0, A.diag[100] + 1e-9, 0.0, 100.0, A.diag[-1]])
     W = ctx.precond_apply(to_dev(R, dt), to_dev(theta, np.float64), kind=L.PRECOND_DIAG).cpu().numpy()
-    ref = diag_precond(R.astype(np.float64), np.asarray(A.diag, dtype=dt).astype(np.float64), theta, 1e-5 * gamma)
+    ref = diag_precond(R.astype(np.float64), np.asarray(A.diag, dtype=dt).astype(np.float64), theta, 1e-5 * gamma,
+                       offset=offset)
     rtol = 1e-6 if f32 else 1e-15
     np.testing.assert_allclose(W, ref, rtol=rtol)
     Wn = ctx.precond_apply(to_dev(R, dt), to_dev(theta, np.float64), kind=L.PRECOND_NONE).cpu().numpy()

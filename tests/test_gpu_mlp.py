@@ -91,9 +91,9 @@ def test_forward_zero_output_and_empty():
     net.forward(f[:0])   # N = 0 is a no-op
 
 
-@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("f32,offset", [(False, 0.0), (True, 0.0), (True, 1.5)])
 @pytest.mark.parametrize("k", [1, 8, 13])
-def test_precond_apply_parity(f32, k):
+def test_precond_apply_parity(f32, k, offset):
     import paper_2109_00485_amd as L
     torch = torch_cuda()
     A = W.make_matrix("random_sym_1k")
@@ -103,6 +103,7 @@ def test_precond_apply_parity(f32, k):
                              sigma=(60.0, 20.0, float(rho.std()), float(tm.std() + 1e-3))))
     net = L.Mlp(blob(p))
     ctx.set_mlp(net)
+    ctx.set_precond_offset(offset)
     rng = np.random.default_rng(k)
     dt = np.float32 if f32 else np.float64
     R = rng.standard_normal((A.n, k)).astype(dt)
@@ -111,7 +112,7 @@ def test_precond_apply_parity(f32, k):
     Wg = ctx.precond_apply(to_dev(R, dt), to_dev(theta, np.float64), kind=L.PRECOND_MLP).cpu().numpy()
     d = np.asarray(A.diag, dtype=dt).astype(np.float64)
     eps = 1e-5 * ctx.query()["gamma"]
-    m_ref = OM.precond_scale(p, d, theta, rho, tm, eps, a1_f32=True)
+    m_ref = OM.precond_scale(p, d, theta, rho, tm, eps, a1_f32=True, offset=offset)
     W_ref = m_ref * R.astype(np.float64)
     # per-entry: the output error of the network plus the rounding of W
     f = np.empty((A.n, k, 4))
@@ -280,17 +281,20 @@ def harvest_inputs(A, nev=5, k=8, seed=0):
     return X, HX, theta, np.ascontiguousarray(xs), rho, t, Hs.gershgorin()
 
 
-def test_harvest_block_parity():
+@pytest.mark.parametrize("offset", [0.0, 2.0])
+def test_harvest_block_parity(offset):
     import paper_2109_00485_amd as L
     torch = torch_cuda()
     A = W.make_matrix("random_sym_1k")
     ctx = upload(A, False)
+    ctx.set_precond_offset(offset)
     X, HX, theta, xs, rho, t, gamma = harvest_inputs(A)
     hb = L.HarvestBuffer(20000, 64, 8, to_dev(xs, np.float64), 5, rows=100, seed=11)
     hb.h.ngroups = 2                      # groups already held: the new ones are 2..6
     ctx.harvest_block(to_dev(X, np.float64), to_dev(HX, np.float64), to_dev(theta, np.float64), hb)
     assert hb.ngroups == 7 and not hb.full
-    ref = OH.harvest_block(X, HX, theta, xs, A.diag, rho, t, 1e-5 * gamma, rows=100, nev=5, seed=11, group0=2)
+    ref = OH.harvest_block(X, HX, theta, xs, A.diag, rho, t, 1e-5 * gamma, rows=100, nev=5, seed=11, group0=2,
+                           offset=offset)
     off = hb.group_off.cpu().numpy()
     rows = hb.row.cpu().numpy()
     f32 = lambda a: np.asarray(a, dtype=np.float32)

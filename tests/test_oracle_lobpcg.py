@@ -119,3 +119,34 @@ def test_recurrence_tracks_explicit_product():
     X, R, theta = seen["X"], seen["R"], seen["theta"]
     Rexp = H @ X - X * theta
     assert np.abs(R - Rexp).max() < 1e-10 * H.gershgorin()
+
+
+def test_precond_offset_by_hand():
+    """sigma_j = theta_j - c (max theta - min theta), W_ij = R_ij / s(d_i - sigma_j)."""
+    from oracle.precond import diag_precond
+    R = np.array([[1.0, 2.0], [3.0, -4.0]])
+    d = np.array([1.0, 4.0])
+    theta = np.array([1.5, 0.5])                 # spread 1.0, unsorted on purpose
+    # c = 0: divisors d - theta = [[-0.5, 0.5], [2.5, 3.5]]
+    np.testing.assert_array_equal(diag_precond(R, d, theta, 1e-3), R / np.array([[-0.5, 0.5], [2.5, 3.5]]))
+    # c = 2: sigma = [-0.5, -1.5], divisors [[1.5, 2.5], [4.5, 5.5]]
+    np.testing.assert_array_equal(diag_precond(R, d, theta, 1e-3, offset=2.0),
+                                  R / np.array([[1.5, 2.5], [4.5, 5.5]]))
+    # the guard still applies to the shifted divisor: d_0 - sigma_0 = 0 -> +eps
+    W = diag_precond(R, d, np.array([1.0, 1.0]), 0.25, offset=3.0)   # spread 0: sigma = theta
+    np.testing.assert_array_equal(W[0], R[0] / 0.25)
+
+
+@pytest.mark.parametrize("offset", [1.0, 2.0])
+def test_precond_offset_solve_vs_dense_eigh(offset):
+    """The shift moved below the Ritz values changes the iterates, not the
+    answer: the same eigenvalues as dense LAPACK, fewer iterations than the
+    shift at the Ritz value on this matrix."""
+    A = W.make_matrix("random_sym_1k")
+    lam = np.linalg.eigvalsh(dense(A))[:5]
+    H, r0 = solve(A)
+    H, r = solve(A, precond_offset=offset)
+    assert r.status == OK
+    np.testing.assert_allclose(r.theta, lam, rtol=1e-9)
+    np.testing.assert_allclose(r.X_all.T @ r.X_all, np.eye(8), atol=1e-10)
+    assert r.iters < r0.iters, (r.iters, r0.iters)
