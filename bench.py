@@ -94,16 +94,26 @@ def learned_vs_diag(args):
     rows = []
     for seed in range(a, b):
         A = W.make_matrix(meta.get("workload", "random_sym_2m"), seed=seed, n=meta.get("n"), f32=True)
-        r = train.compare(A, net, k=8, nev=5, tol=1e-6)
+        offset = float(meta.get("offset", 0.0))
+        r = train.compare(A, net, k=8, nev=5, tol=1e-6, offset=offset)
         rows.append(dict(seed=seed, **{k_: {kk: v[kk] for kk in ("iters", "seconds", "status", "rel")}
                                          for k_, v in r.items()}))
+        extra = f" | diag at theta_j {r['diag_theta']['iters']} it {r['diag_theta']['seconds']:.3f} s" \
+            if "diag_theta" in r else ""
         log(f"learned vs diag, seed {seed}: diag {r['diag']['iters']} it {r['diag']['seconds']:.3f} s | "
-            f"mlp {r['mlp']['iters']} it {r['mlp']['seconds']:.3f} s")
-    di = np.mean([x["diag"]["iters"] for x in rows]); mi = np.mean([x["mlp"]["iters"] for x in rows])
-    ds = np.mean([x["diag"]["seconds"] for x in rows]); ms = np.mean([x["mlp"]["seconds"] for x in rows])
-    return dict(workload=meta.get("workload", "random_sym_2m"), seeds=args.learned_seeds, weights=os.path.relpath(WEIGHTS, ROOT),
-                diag_iters=di, mlp_iters=mi, diag_seconds=round(ds, 4), mlp_seconds=round(ms, 4),
-                speedup=round(ds / ms, 3) if ms > 0 else None, runs=rows)
+            f"mlp {r['mlp']['iters']} it {r['mlp']['seconds']:.3f} s{extra}")
+    mean = lambda key, f: float(np.mean([x[key][f] for x in rows])) if all(key in x for x in rows) else None
+    di, mi, ds, ms = mean("diag", "iters"), mean("mlp", "iters"), mean("diag", "seconds"), mean("mlp", "seconds")
+    out = dict(workload=meta.get("workload", "random_sym_2m"), seeds=args.learned_seeds,
+               weights=os.path.relpath(WEIGHTS, ROOT), offset=float(meta.get("offset", 0.0)),
+               diag_iters=di, mlp_iters=mi, diag_seconds=round(ds, 4), mlp_seconds=round(ms, 4),
+               speedup=round(ds / ms, 3) if ms > 0 else None)
+    if mean("diag_theta", "iters") is not None:
+        # the diagonal step with the shift at theta_j (offset 0), the plain baseline
+        out.update(diag_theta_iters=mean("diag_theta", "iters"), diag_theta_seconds=round(mean("diag_theta", "seconds"), 4),
+                   speedup_vs_diag_theta=round(mean("diag_theta", "seconds") / ms, 3) if ms > 0 else None)
+    out["runs"] = rows
+    return out
 
 
 def cpu_baseline(A, k, budget_s=15.0):
@@ -148,6 +158,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--other-starts", type=lambda v: [int(x) for x in v.split(",") if x], default=[2, 3, 4],
                     help="comma-separated seeds of extra starting blocks solved once each (reported only)")
+    ap.add_argument("--offset", type=float, default=4.0,
+                    help="also solve with the diagonal shift this many Ritz-value spreads below theta_j (0: skip)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-diagonal preconditioner comparison")
     ap.add_argument("--learned-seeds", default="1000:1002",
@@ -236,6 +248,50 @@ def main():
     gbs = nbytes / (t_spmm / n_spmm) / 1e9
     last = results[-1]
     traffic, tnote = counter_traffic(args.workload, args.k)
+    # the same solve with the diagonal shift held --offset Ritz-value spreads below theta_j
+    solve_offset = None
+    if args.offset > 0:
+        ctx.set_precond_offset(args.offset)
+        ro, secs = None, []
+        for rep in range(1 + args.steps):   # one warm-up, then timed like the diagonal steps
+            Xo = X0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ro = ctx.solve(Xo, args.nev, tol=args.tol, maxiter=args.maxiter)
+            torch.cuda.synchronize()
+            if rep:
+                secs.append(time.perf_counter() - t0)
+        ctx.set_precond_offset(0.0)
+        solve_offset = dict(offset=args.offset, seconds=round(float(np.mean(secs)), 4), iters=ro.iters,
+                            status=ro.status, evals=[float(x) for x in ro.evals[:args.nev]])
+        log(f"diagonal shift {args.offset} spreads below theta_j: status {ro.status} iters {ro.iters} "
+            f"{solve_offset['seconds']} s")
+    # the same solve with this workload's trained network preconditioner, when one is shipped
+    solve_learned = None
+    wpath = os.path.join(ROOT, "paper_2109_00485_amd", "weights", f"{args.workload}.json")
+    if not args.no_learned and os.path.exists(wpath) and args.n is None:
+        from paper_2109_00485_amd import train
+        blob, meta = train.load_params(wpath)
+        net = L.Mlp(blob)
+        ctx.set_mlp(net)
+        ctx.set_precond_offset(float(meta.get("offset", 0.0)))
+        rl = None
+        secs = []
+        for rep in range(1 + args.steps):   # one warm-up, then timed like the diagonal steps
+            Xl = X0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rl = ctx.solve(Xl, args.nev, tol=args.tol, maxiter=args.maxiter, precond=L.PRECOND_MLP)
+            torch.cuda.synchronize()
+            if rep:
+                secs.append(time.perf_counter() - t0)
+        ctx.set_mlp(None)
+        ctx.set_precond_offset(0.0)
+        solve_learned = dict(seconds=round(float(np.mean(secs)), 4), iters=rl.iters, status=rl.status,
+                             evals=[float(x) for x in rl.evals[:args.nev]],
+                             weights=os.path.relpath(wpath, ROOT), trained_on_seeds=meta.get("train_seeds"),
+                             offset=float(meta.get("offset", 0.0)))
+        log(f"learned preconditioner on this matrix: status {rl.status} iters {rl.iters} {solve_learned['seconds']} s")
     # the iteration count from a random start depends on rounding (the shifted
     # diagonal preconditioner is nearly singular while theta is far above the
     # wanted eigenvalues): report solves from a few other Gaussian starts too
@@ -268,6 +324,8 @@ def main():
                   "status": last.status, "evals": [float(x) for x in last.evals[:args.nev]],
                   "phase_s": {k_: round(v / args.steps if False else v, 4) for k_, v in last.times.items()}},
         "solve_other_starts": other_starts,
+        "solve_offset": solve_offset,
+        "solve_learned": solve_learned,
         "spmm_standalone_ms": round(spmm_ms, 4),
         "spmm_in_solve_ms": round(spmm_in_solve_ms, 4),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -19,6 +19,26 @@ constexpr int NMAX = 48;
 constexpr int LD = NMAX + 1;
 constexpr int KM_CHOL = 16;   // Cholesky QR block width bound (kmax)
 
+// 1/x and 1/sqrt(x) for positive normal x: the hardware estimates refined by
+// two Newton steps (each doubles the correct bits; a few ulp at the end).  A
+// Jacobi rotation needs c^2 + s^2 = 1 to rounding, not correctly rounded
+// quotients, and this chain is on the critical path of every round.
+__device__ inline double recip_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ inline double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
@@ -279,10 +299,11 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
                     if (q < N) {
                         const double g2 = 2.0 * A[p * LD + q];
                         const double h = A[q * LD + q] - A[p * LD + p];
-                        const double rad = sqrt(h * h + g2 * g2);
-                        if (g2 != 0.0 && rad > 0.0) {   // rad = 0: both below the square's range, no rotation
-                            const double tt = (h >= 0 ? g2 : -g2) / (fabs(h) + rad);
-                            c = 1.0 / sqrt(1.0 + tt * tt);
+                        const double r2 = h * h + g2 * g2;
+                        if (g2 != 0.0 && r2 >= DBL_MIN) {   // below: both negligible, no rotation
+                            const double rad = r2 * rsqrt_nr(r2);
+                            const double tt = (h >= 0 ? g2 : -g2) * recip_nr(fabs(h) + rad);
+                            c = rsqrt_nr(fma(tt, tt, 1.0));
                             sn = tt * c;
                         }
                     }

@@ -11,6 +11,11 @@ only orders the calls and moves device buffers between them):
   4. evaluation: the same solve with the diagonal and with the learned
      preconditioner, compared by iterations, wall-clock and final residual.
 
+The network scales the diagonal step 1/s(d_i - sigma_j); sigma_j = theta_j -
+offset * (Ritz-value spread) (offset 0: the Ritz value itself).  A network is
+trained for one offset, recorded with its weights, and must be used with the
+same offset (Context.set_precond_offset).
+
 Command line (synthetic matrices of a named workload, weights written as
 JSON):  python -m paper_2109_00485_amd.train --workload random_sym_2m \
             --train-seeds 0:16 --eval-seeds 1000:1020 --out weights.json
@@ -60,11 +65,12 @@ def _log(msg):
 
 
 def harvest_matrix(A, hb: HarvestBuffer, *, k=8, nev=5, every=10, rows=256, seed=0, tol_star=1e-9, tol=1e-6,
-                   maxiter=5000, x0_seed=1):
+                   maxiter=5000, x0_seed=1, offset=0.0):
     """Append one matrix's samples to hb (FP64 context for both passes)."""
     import torch
     from synth import workloads as W
     ctx = Context.from_csr(A, dtype=F64)
+    ctx.set_precond_offset(offset)
     X0 = torch.from_numpy(W.initial_block(A.n, k, seed=x0_seed)).cuda()
     Xs = X0.clone()
     r_star = ctx.solve(Xs, nev, tol=tol_star, maxiter=maxiter)
@@ -89,8 +95,10 @@ def fit(net: Mlp, batch, steps=1500, lr=3e-3, lr_end=3e-4, log_every=100):
     return losses
 
 
-def compare(A, net: Mlp, *, k=8, nev=5, tol=1e-6, maxiter=5000, x0_seed=1, f32=True):
-    """Diagonal vs learned preconditioner on one matrix: iterations, seconds, final residuals."""
+def compare(A, net: Mlp, *, k=8, nev=5, tol=1e-6, maxiter=5000, x0_seed=1, f32=True, offset=0.0):
+    """Diagonal vs learned preconditioner on one matrix: iterations, seconds, final
+    residuals.  "diag" is the diagonal step the network was trained on (shift
+    offset ``offset``); with offset > 0, "diag_theta" is the shift at theta_j."""
     import torch
     from synth import workloads as W
     ctx = Context.from_csr(A, dtype=F32 if f32 else F64)
@@ -98,7 +106,11 @@ def compare(A, net: Mlp, *, k=8, nev=5, tol=1e-6, maxiter=5000, x0_seed=1, f32=T
     dt = np.float32 if f32 else np.float64
     X0 = torch.from_numpy(W.initial_block(A.n, k, seed=x0_seed, dtype=dt)).cuda()
     out = {}
-    for name, pc in (("diag", PRECOND_DIAG), ("mlp", PRECOND_MLP)):
+    runs = [("diag", PRECOND_DIAG, offset), ("mlp", PRECOND_MLP, offset)]
+    if offset > 0:
+        runs.append(("diag_theta", PRECOND_DIAG, 0.0))
+    for name, pc, c in runs:
+        ctx.set_precond_offset(c)
         X = X0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -132,6 +144,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--lr-end", type=float, default=3e-4)
     ap.add_argument("--init-seed", type=int, default=0)
+    ap.add_argument("--offset", type=float, default=0.0,
+                    help="diagonal preconditioner shift offset, in Ritz-value spreads below theta_j")
     ap.add_argument("--out", required=True)
     ap.add_argument("--report", default=None, help="JSON report of the evaluation")
     args = ap.parse_args(argv)
@@ -145,7 +159,8 @@ def main(argv=None):
     for seed in _seeds(args.train_seeds):
         t0 = time.time()
         A = W.make_matrix(args.workload, seed=seed, n=args.n, f32=False)
-        info = harvest_matrix(A, hb, k=args.k, nev=args.nev, every=args.every, rows=args.rows, seed=seed)
+        info = harvest_matrix(A, hb, k=args.k, nev=args.nev, every=args.every, rows=args.rows, seed=seed,
+                              offset=args.offset)
         runs.append(dict(seed=seed, **info))
         _log(f"seed {seed}: {info} samples {hb.nsamples} ({time.time() - t0:.1f}s)")
         if hb.full:
@@ -161,7 +176,8 @@ def main(argv=None):
     t_train = time.time() - t0
     _log(f"trained {args.steps} steps on {hb.nsamples} samples / {hb.ngroups} groups in {t_train:.1f}s: "
          f"loss {losses[0]:.5f} -> {losses[-1]:.5f}")
-    meta = dict(workload=args.workload, n=args.n, train_seeds=args.train_seeds, every=args.every, rows=args.rows,
+    meta = dict(workload=args.workload, n=args.n, train_seeds=args.train_seeds, offset=args.offset,
+                every=args.every, rows=args.rows,
                 steps=args.steps, lr=args.lr, lr_end=args.lr_end, samples=hb.nsamples, groups=hb.ngroups,
                 loss_first=losses[0], loss_last=losses[-1], train_seconds=t_train)
     blob = net.params()
@@ -169,18 +185,22 @@ def main(argv=None):
     evals = []
     for seed in _seeds(args.eval_seeds):
         A = W.make_matrix(args.workload, seed=seed, n=args.n, f32=True)
-        res = compare(A, net, k=args.k, nev=args.nev)
+        res = compare(A, net, k=args.k, nev=args.nev, offset=args.offset)
         evals.append(dict(seed=seed, **res))
+        extra = f" | diag at theta {res['diag_theta']['iters']} it" if "diag_theta" in res else ""
         _log(f"eval {seed}: diag {res['diag']['iters']} it {res['diag']['seconds']:.3f}s | "
-             f"mlp {res['mlp']['iters']} it {res['mlp']['seconds']:.3f}s")
+             f"mlp {res['mlp']['iters']} it {res['mlp']['seconds']:.3f}s{extra}")
     report = dict(meta=meta, runs=runs, eval=evals, losses=losses[:: max(1, len(losses) // 100)],
                   total_seconds=time.time() - t_start)
     if evals:
         di = np.array([e["diag"]["iters"] for e in evals]); mi = np.array([e["mlp"]["iters"] for e in evals])
         ds = np.array([e["diag"]["seconds"] for e in evals]); ms = np.array([e["mlp"]["seconds"] for e in evals])
-        report["summary"] = dict(diag_iters_mean=float(di.mean()), mlp_iters_mean=float(mi.mean()),
+        report["summary"] = dict(offset=args.offset, diag_iters_mean=float(di.mean()), mlp_iters_mean=float(mi.mean()),
                                  diag_seconds_mean=float(ds.mean()), mlp_seconds_mean=float(ms.mean()),
                                  iters_ratio=float(mi.mean() / di.mean()), seconds_ratio=float(ms.mean() / ds.mean()))
+        if all("diag_theta" in e for e in evals):
+            report["summary"]["diag_theta_iters_mean"] = float(np.mean([e["diag_theta"]["iters"] for e in evals]))
+            report["summary"]["diag_theta_seconds_mean"] = float(np.mean([e["diag_theta"]["seconds"] for e in evals]))
         _log(f"summary: {report['summary']}")
     if args.report:
         with open(args.report, "w") as fh:

@@ -101,19 +101,59 @@ def test_block_sizes_against_dense_spectrum(k, nev):
 @pytest.mark.parametrize("f32", [False, True])
 def test_precond_offset_solve(f32):
     """Shift two Ritz-value spreads below theta_j: the same eigenpairs as the
-    oracle run with the same shift, in about as many iterations (FP64 follows
-    the oracle's steps; rounding differences change the count slightly)."""
+    oracle run with the same shift, and far fewer iterations than with the
+    shift at theta_j.  (Iteration counts themselves are not compared with the
+    oracle's: rounding differences grow along the trajectory, and on this
+    matrix equally valid runs take between ~60 and ~100 iterations.)"""
     A = W.make_matrix("random_sym_20k")
     H, ref = oracle_solve("rs20k", A, precond_offset=2.0)
-    import paper_2109_00485_amd as L
     ctx = upload(A, f32)
-    ctx.set_precond_offset(2.0)
     dt = np.float32 if f32 else np.float64
-    X = to_dev(W.initial_block(A.n, 8, seed=1), dt)
+    X0 = W.initial_block(A.n, 8, seed=1)
+    r0 = ctx.solve(to_dev(X0, dt), 5, maxiter=5000)
+    ctx.set_precond_offset(2.0)
+    X = to_dev(X0, dt)
     r = ctx.solve(X, 5, maxiter=5000)
-    assert r.status == 0, r
+    assert r.status == 0 and r0.status == 0, (r, r0)
     check_against_oracle(H, ref, r, X.cpu().numpy().astype(np.float64), f32)
-    assert abs(r.iters - ref.iters) <= max(5, 0.1 * ref.iters), (r.iters, ref.iters)
+    print(f"iterations: shift at theta_j {r0.iters}, offset 2: {r.iters} (oracle {ref.iters})")
+    assert r.iters < 0.6 * r0.iters, (r.iters, r0.iters)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_solve_repeatable_after_other_solves(f32):
+    """A solve depends only on its inputs: the same start on the same context
+    gives bitwise the same iterates, vectors and values, also after solves
+    with another shift offset and with the network preconditioner in between
+    (no state carries over from one call to the next)."""
+    import paper_2109_00485_amd as L
+    from paper_2109_00485_amd import train
+    A = W.make_matrix("random_sym_20k")
+    ctx = upload(A, f32)
+    dt = np.float32 if f32 else np.float64
+    X0 = W.initial_block(A.n, 8, seed=1)
+
+    def run(**kw):
+        X = to_dev(X0, dt)
+        r = ctx.solve(X, 5, maxiter=5000, history=True, **kw)
+        return r, X.cpu().numpy()
+
+    r1, X1 = run()
+    ctx.set_precond_offset(4.0)
+    run()
+    net = L.Mlp(train.init_params(7))
+    ctx.set_mlp(net)
+    run(precond=L.PRECOND_MLP)
+    ctx.set_precond_offset(0.0)
+    r2, X2 = run()
+    assert r1.iters == r2.iters
+    assert np.array_equal(r1.evals, r2.evals)
+    assert np.array_equal(X1, X2)
+    assert np.array_equal(r1.theta_hist, r2.theta_hist)
+    ctx2 = upload(A, f32)
+    X = to_dev(X0, dt)
+    r3 = ctx2.solve(X, 5, maxiter=5000)
+    assert r3.iters == r1.iters and np.array_equal(r3.evals, r1.evals) and np.array_equal(X.cpu().numpy(), X1)
 
 
 def test_bf16x3_gram_solve():
