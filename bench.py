@@ -162,7 +162,7 @@ def main():
                     help="also solve with the diagonal shift this many Ritz-value spreads below theta_j (0: skip)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-diagonal preconditioner comparison")
-    ap.add_argument("--learned-seeds", default="1000:1002",
+    ap.add_argument("--learned-seeds", default="1000:1006",
                     help="evaluation matrices (seeds) of the learned-preconditioner workload")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only time the sparse product (profiling runs); prints one JSON line")
@@ -205,6 +205,25 @@ def main():
     torch.cuda.synchronize()
     spmm_ms = s0.elapsed_time(s1) / args.spmm_reps
     log(f"standalone spmm: {spmm_ms:.3f} ms, {nbytes / spmm_ms / 1e6:.1f} GB/s")
+    copy_gbs = None
+    if not args.spmm_only:
+        # achievable HBM bandwidth on this GPU: a plain 2 GiB device copy (reads
+        # 2 GiB, writes 2 GiB; 8x the 256 MB last-level cache), HIP events
+        a = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(2):
+            b.copy_(a)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            b.copy_(a)
+        c1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * a.numel() * 4 / (c0.elapsed_time(c1) / 5) / 1e6
+        del a, b
+        torch.cuda.empty_cache()
+        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     if args.spmm_only:
         out = {"mode": "spmm-only", "workload": args.workload, "n": A.n, "nnz_stored": A.nnz, "format": q["format"],
                "k": args.k, "reps": args.spmm_reps,
@@ -332,7 +351,12 @@ def main():
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else int(traffic),
                      "kernel": f"spmm ({q['format']}) k={args.k}",
-                     "bytes_per_launch": int(nbytes), "traffic_note": tnote},
+                     "bytes_per_launch": int(nbytes), "traffic_note": tnote,
+                     # the same kernel against the copy bandwidth measured above, and the
+                     # rate of the bytes it actually moves (counter traffic / launch time)
+                     "copy_GBps": None if copy_gbs is None else round(copy_gbs, 1),
+                     "frac_of_copy": None if copy_gbs is None else round(gbs / copy_gbs, 4),
+                     "traffic_GBps": None if traffic is None else round(traffic / (spmm_in_solve_ms * 1e6), 1)},
     }
     if not args.no_learned:
         try:

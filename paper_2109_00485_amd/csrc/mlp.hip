@@ -123,6 +123,15 @@ __device__ inline float mlp_step(const LaneWeights &L, float z) {
 // trained network reweights the diagonal step by a factor in [e^-2, e^2].
 constexpr float OUT_BOUND = 2.0f;
 
+// exp(2 tanh(o / 2)) from two hardware exponentials: with u = exp(-|o|),
+// tanh(|o| / 2) = (1 - u) / (1 + u).  Relative error a few 1e-7 (the
+// cancellation in 1 - u is absolute, and exp(2 tanh) ~ 1 + 2 tanh there).
+__device__ inline float bounded_scale_fast(float o) {
+    const float u = __expf(-fabsf(o));
+    const float th = (1.0f - u) * __builtin_amdgcn_rcpf(1.0f + u);
+    return __expf(OUT_BOUND * copysignf(th, o));
+}
+
 // W = m o R with m_ij = exp(b(o_ij)) / s(d_i - sigma_j), sigma_j the diagonal
 // preconditioner's shift of column j; R may alias W.
 // KP > 0 fixes k at compile time (the sample -> (row, column) split is a shift).
@@ -177,13 +186,15 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int
         if (g == 0 && sidx < total) {
             const double dm = cur.f - cur.th + lift;
             const double sg = fabs(dm) >= eps ? dm : (dm < 0 ? -eps : eps);
-            const float e = expf(OUT_BOUND * tanhf(o / OUT_BOUND));
             if constexpr (sizeof(T) == 4) {
-                // FP32 blocks: the scale in FP32 (the guard decision stays in FP64)
-                float m = e / (float)sg;
-                if (!isfinite(m)) m = 1.0f / (float)sg;
+                // FP32 blocks: the scale in FP32 from hardware exponentials and
+                // reciprocal (a few ulp; the guard decision stays in FP64)
+                const float rs = __builtin_amdgcn_rcpf((float)sg);
+                float m = bounded_scale_fast(o) * rs;
+                if (!isfinite(m)) m = rs;
                 W[sidx] = cur.r * m;
             } else {
+                const float e = expf(OUT_BOUND * tanhf(o / OUT_BOUND));
                 double m = (double)e / sg;
                 if (!isfinite(m)) m = 1.0 / sg;
                 W[sidx] = cur.r * m;
