@@ -25,6 +25,7 @@
  * uniforms), which is exact in distribution and O(n).
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
@@ -142,11 +143,19 @@ static void emit_scatter(void *ectx, int64_t lo, int64_t hi, double v) {
     s->v[pos] = v;
 }
 
+/* stage lines on stderr when SYNTH_PROGRESS is set (large matrices take minutes) */
+static void progress(const char *stage, int64_t n, int64_t count) {
+    if (!getenv("SYNTH_PROGRESS")) return;
+    fprintf(stderr, "[synth] n=%lld: %s (%lld)\n", (long long)n, stage, (long long)count);
+    fflush(stderr);
+}
+
 static synth_csr *assemble(int64_t n, const double *diag, pair_emit_fn gen, void *gctx, int f32) {
     int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     if (!cnt) return NULL;
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) gen(gctx, i, emit_count, cnt);
+    progress("pairs counted", n, n);
     int64_t *off = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
     off[0] = 0;
     for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + cnt[i];
@@ -159,6 +168,7 @@ static synth_csr *assemble(int64_t n, const double *diag, pair_emit_fn gen, void
     if (!sc.hi || !sc.v) { free(cnt); free(off); free(sc.hi); free(sc.v); return NULL; }
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) gen(gctx, i, emit_scatter, &sc);
+    progress("pairs placed", n, raw);
     /* sort each bucket by column, merge duplicate pairs by summation */
     int64_t *fcnt = cnt; /* reuse: final off-diagonal count per row */
     #pragma omp parallel
@@ -181,6 +191,7 @@ static synth_csr *assemble(int64_t n, const double *diag, pair_emit_fn gen, void
         }
         free(buf);
     }
+    progress("rows sorted and merged", n, n);
     synth_csr *h = (synth_csr *)calloc(1, sizeof(synth_csr));
     h->n = n; h->f32 = f32;
     h->row_ptr = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
@@ -206,6 +217,7 @@ static synth_csr *assemble(int64_t n, const double *diag, pair_emit_fn gen, void
         }
     }
     free(cnt); free(off); free(sc.hi); free(sc.v);
+    progress("CSR built", n, h->nnz);
     return h;
 }
 
