@@ -150,11 +150,25 @@ static void progress(const char *stage, int64_t n, int64_t count) {
     fflush(stderr);
 }
 
+/* rows done in a generator pass; a stage line at every tenth of the rows */
+static void rows_done(const char *stage, int64_t n, int64_t *done, int64_t add) {
+    int64_t before;
+    #pragma omp atomic capture
+    { before = *done; *done += add; }
+    const int64_t step = n / 10 > 0 ? n / 10 : 1;
+    if ((before + add) / step != before / step) progress(stage, n, before + add);
+}
+
 static synth_csr *assemble(int64_t n, const double *diag, pair_emit_fn gen, void *gctx, int f32) {
     int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     if (!cnt) return NULL;
-    #pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t i = 0; i < n; ++i) gen(gctx, i, emit_count, cnt);
+    int64_t done = 0;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < n; b += 4096) {
+        const int64_t e = b + 4096 < n ? b + 4096 : n;
+        for (int64_t i = b; i < e; ++i) gen(gctx, i, emit_count, cnt);
+        rows_done("counting pairs, rows", n, &done, e - b);
+    }
     progress("pairs counted", n, n);
     int64_t *off = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
     off[0] = 0;
@@ -166,16 +180,23 @@ static synth_csr *assemble(int64_t n, const double *diag, pair_emit_fn gen, void
     sc.hi = (int32_t *)malloc((size_t)(raw ? raw : 1) * sizeof(int32_t));
     sc.v = (double *)malloc((size_t)(raw ? raw : 1) * sizeof(double));
     if (!sc.hi || !sc.v) { free(cnt); free(off); free(sc.hi); free(sc.v); return NULL; }
-    #pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t i = 0; i < n; ++i) gen(gctx, i, emit_scatter, &sc);
+    done = 0;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < n; b += 4096) {
+        const int64_t e = b + 4096 < n ? b + 4096 : n;
+        for (int64_t i = b; i < e; ++i) gen(gctx, i, emit_scatter, &sc);
+        rows_done("placing pairs, rows", n, &done, e - b);
+    }
     progress("pairs placed", n, raw);
     /* sort each bucket by column, merge duplicate pairs by summation */
     int64_t *fcnt = cnt; /* reuse: final off-diagonal count per row */
+    done = 0;
     #pragma omp parallel
     {
         size_t cap = 0; ent_t *buf = NULL;
         #pragma omp for schedule(dynamic, 256)
         for (int64_t i = 0; i < n; ++i) {
+            if ((i & 4095) == 4095) rows_done("sorting rows", n, &done, 4096);
             int64_t b = off[i], e = off[i + 1], m = e - b;
             if ((size_t)m > cap) { cap = (size_t)m * 2; buf = (ent_t *)realloc(buf, cap * sizeof(ent_t)); }
             for (int64_t q = 0; q < m; ++q) { buf[q].c = sc.hi[b + q]; buf[q].v = sc.v[b + q]; }
