@@ -73,3 +73,31 @@ def test_entry_points_reject_null_context(lib):
     assert lib.lobpcg_query(None, None, None, None, None, None) == L.EINVAL
     assert lib.lobpcg_last_error(None) == b"null context"
     lib.lobpcg_destroy(None)
+    assert lib.lobpcg_set_precond_offset(None, 1.0) == L.EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; asking for more exits with a message, before
+    any device is touched."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_committed_counter_summary_parses():
+    """The FETCH/WRITE counter summary that bench.py turns into roofline.traffic
+    is readable and gives a positive byte count per product (it is reported as
+    null instead when the sparse-product source has changed since)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    t, note = bench.counter_traffic("tiled_2m", 8)
+    if t is None:
+        assert note == "kernel sources changed since the counters were taken"
+    else:
+        assert 3.3e9 < t < 1e11 and note["fetch_scale"] > 0 and note["write_scale"] > 0
