@@ -53,7 +53,7 @@ extern "C" {
 #define LOBPCG_GRAM_BF16X3 3     /* split-BF16 (a0b0 + a0b1 + a1b0) MFMA, FP32 inputs */
 
 #define LOBPCG_PRECOND_NONE 0    /* K = I                                       */
-#define LOBPCG_PRECOND_DIAG 1    /* W_ij = R_ij / s(d_i - theta_j)              */
+#define LOBPCG_PRECOND_DIAG 1    /* W_ij = R_ij / s(d_i - sigma_j), sigma_j = theta_j by default */
 #define LOBPCG_PRECOND_MLP  2    /* learned scaling from an attached MLP        */
 
 #define LOBPCG_FORMAT_AUTO  0    /* tiled when tiles are dense enough, else CSR */
@@ -193,8 +193,9 @@ int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *X, double *evals, double
  * Learned preconditioner.
  *
  * The paper's preconditioner (Section 3.4) is a shifted diagonal solve; its
- * 1 x 1-tile form is W_ij = R_ij / s(d_i - theta_j).  The learned variant keeps
- * that form and multiplies it by exp(2 tanh(o_ij / 2)) (a factor in
+ * 1 x 1-tile form is W_ij = R_ij / s(d_i - sigma_j) (sigma_j = theta_j unless the
+ * context's offset moves it, lobpcg_set_precond_offset).  The learned variant
+ * keeps that form and multiplies it by exp(2 tanh(o_ij / 2)) (a factor in
  * [e^-2, e^2]), where o_ij is the output of a
  * 4 -> 64 -> 64 -> 1 ReLU network of the standardised per-entry features
  *     f_ij = (d_i, theta_j, rho_i, t_i),  z = (f - mu) / sigma,
@@ -246,7 +247,7 @@ int lobpcg_mlp_fit_standardizer(lobpcg_mlp *m, const float *feat, int64_t N, voi
 /* A training batch: samples grouped by (run, iteration, column j); the rows
  * of one group are contiguous.  Per sample s of group g:
  *   feat  raw features (d_i, theta_j, rho_i, t_i)
- *   U     the diagonal step R_ij / s(d_i - theta_j)
+ *   U     the diagonal step R_ij / s(d_i - sigma_j) of the harvesting context
  *   T     the exact correction of column j at row i (its error outside span X)
  *   w     importance weight of the sampled row
  *   Xrow  row i of the block X (k values)

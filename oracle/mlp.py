@@ -1,9 +1,10 @@
 """FP64 oracle of the learned preconditioner network (test infrastructure).
 
-The network replaces the diagonal shift-inverse 1/s(d_i - theta_j) of the
-preconditioner (Section 3.4 with 1 x 1 tiles) by a learned per-entry scale
+The network replaces the diagonal shift-inverse 1/s(d_i - sigma_j) of the
+preconditioner (Section 3.4 with 1 x 1 tiles; sigma_j = theta_j unless an
+offset moves the shift, see oracle.precond) by a learned per-entry scale
 
-    m_ij = exp(b(o_ij)) / s(d_i - theta_j),   W_ij = m_ij R_ij,
+    m_ij = exp(b(o_ij)) / s(d_i - sigma_j),   W_ij = m_ij R_ij,
     b(o) = C tanh(o / C),  C = OUT_BOUND = 2,
 
 so the network can reweight an entry of the diagonal step by a factor in

@@ -3,7 +3,8 @@
 // For a block X with H X, Ritz values theta and converged eigenvectors x* of
 // the same matrix, each column j < nev yields one group of samples:
 //   E_j = x*_j - X (X^T x*_j)          the exact correction outside span(X)
-//   R_ij = (H X)_ij - theta_j X_ij     the residual, U_ij = R_ij / s(d_i - theta_j)
+//   R_ij = (H X)_ij - theta_j X_ij     the residual, U_ij = R_ij / s(d_i - sigma_j)
+//   (sigma_j the context's diagonal-preconditioner shift, theta_j by default)
 // Row i enters the group with probability
 //   p_i = min(1, rows (1/(2n) + |E_ij| / (2 sum_l |E_lj|)))
 // (half uniform, half proportional to |E|), decided by a uniform draw from

@@ -1,5 +1,5 @@
 // Learned preconditioner network 4 -> 64 -> 64 -> 1 (the preconditioner
-// scale is exp(2 tanh(o / 2)) / s(d - theta)).
+// scale is exp(2 tanh(o / 2)) / s(d - sigma), sigma the diagonal step's shift).
 //
 // Inference (the preconditioner apply and lobpcg_mlp_forward) runs on the
 // matrix cores, 16 samples per wavefront step, with both hidden layers
