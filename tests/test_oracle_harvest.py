@@ -86,3 +86,22 @@ def test_residual_step_fields():
     mask = np.abs(den) >= eps
     assert np.allclose(out["U"][mask] * den[mask], R[mask], rtol=1e-14, atol=1e-15)
     assert np.array_equal(out["feat"][:, 2], np.arange(400.0)) and np.all(out["feat"][:, 1] == th[0])
+
+
+
+def test_residual_step_with_shift_offset():
+    """U_ij = R_ij / s(d_i - sigma_j), sigma_j = theta_j - c (max theta - min theta):
+    the harvested step is the shifted diagonal step (here computed by hand)."""
+    rng, X, HX, th, xs, d = _setup()
+    eps = 1e-3
+    c = 3.0
+    out = H.harvest_block(X, HX, th, xs, d, np.arange(400.0), np.arange(400.0) * 2, eps, rows=800, nev=2,
+                          seed=0, group0=0, offset=c)
+    for j in range(2):
+        R = HX[:, j] - X[:, j] * th[j]
+        sigma = th[j] - c * (th.max() - th.min())
+        den = d - sigma
+        o = out[j]
+        mask = np.abs(den[o["row"]]) >= eps
+        assert np.allclose(o["U"][mask] * den[o["row"]][mask], R[o["row"]][mask], rtol=1e-14, atol=1e-15)
+        assert np.all(o["feat"][:, 1] == th[j])      # the feature stays the Ritz value itself

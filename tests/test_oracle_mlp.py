@@ -53,6 +53,17 @@ def test_zero_output_is_diagonal():
     assert np.array_equal(m, 1.0 / mlp.guard(d[:, None] - theta[None, :], 0.1))
 
 
+
+def test_zero_output_is_offset_diagonal():
+    """With the shift moved c spreads below theta (sigma = theta - c (max - min)),
+    a zero network is exactly the shifted diagonal step: spread 3.5, c = 2 gives
+    sigma = theta - 7."""
+    p = mlp.init_params(0)
+    d = np.linspace(0, 10, 50)
+    theta = np.array([-1.0, 0.0, 2.5])
+    m = mlp.precond_scale(p, d, theta, np.ones(50), np.ones(50), eps=0.1, offset=2.0)
+    assert np.array_equal(m, 1.0 / mlp.guard(d[:, None] - (theta - 7.0)[None, :], 0.1))
+
 def synthetic_batch(seed, ngroups=6, per=40, k=3):
     rng = np.random.default_rng(seed)
     N = ngroups * per
