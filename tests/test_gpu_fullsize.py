@@ -31,13 +31,19 @@ def tiled():
     return _CACHE["tiled"]
 
 
-def sampled_row_error(ctx, H, n, k, seed, nrows=3000):
+def sampled_row_error(ctx, H, n, k, seed, nrows=3000, plain=False):
+    """Largest ||Y_i - (HX)_i|| / ||(|H||X|)_i|| over sampled rows (and, with
+    plain=True, also the largest ||Y_i - (HX)_i|| / ||(HX)_i||)."""
     rows = np.sort(np.random.default_rng(seed).choice(n, nrows, replace=False))
     rows[0], rows[-1] = 0, n - 1          # first and last rows (ragged last tile)
     X = W.initial_block(n, k, seed=seed, dtype=np.float32)
     Y = ctx.spmm_sym(to_dev(X, np.float32)).cpu().numpy()
     y, yabs = H.rows(X.astype(np.float64), rows)
-    return float(np.max(np.linalg.norm(Y[rows].astype(np.float64) - y, axis=1) / np.linalg.norm(yabs, axis=1)))
+    dy = np.linalg.norm(Y[rows].astype(np.float64) - y, axis=1)
+    scaled = float(np.max(dy / np.linalg.norm(yabs, axis=1)))
+    if plain:
+        return scaled, float(np.max(dy / np.linalg.norm(y, axis=1)))
+    return scaled
 
 
 @pytest.mark.parametrize("k", [8, 16])
@@ -47,7 +53,10 @@ def test_tiled_2m_spmm_sampled_rows(k):
     A, H = tiled()
     ctx = upload(A, True)
     assert ctx.query()["format"] == L.FORMAT_TILED
-    assert sampled_row_error(ctx, H, A.n, k, seed=k) <= 1e-5
+    scaled, plain = sampled_row_error(ctx, H, A.n, k, seed=k, plain=True)
+    print(f"k={k}: max row error {scaled:.3g} of ||(|H||X|)_i||, {plain:.3g} of ||(HX)_i||")
+    # the FP32 bar holds against both row scales
+    assert scaled <= 1e-5 and plain <= 1e-5
     ctx.close()
     torch.cuda.synchronize()
 
@@ -64,6 +73,8 @@ def test_tiled_2m_solve_certified():
     th = r.evals[:5]
     res = np.linalg.norm(HX[:, :5] - Xg[:, :5] * th, axis=0) / np.linalg.norm(Xg[:, :5], axis=0)
     tau = 1e-3 * H.gershgorin()
+    print(f"theta {th}; true residual {res}; relative to |theta| {res / np.abs(th)}; "
+          f"relative to max(|theta|, tau) {res / np.maximum(np.abs(th), tau)} (tau {tau:.3g})")
     # the solver's test (rel <= 1e-6) on the true residual: an FP64 product of the FP32
     # vectors, which differs from the solver's FP32 one by the FP32 product's rounding
     # (~1e-7 of the row scale); every reported value is within ||r|| / ||x|| of an
