@@ -65,15 +65,20 @@ def _log(msg):
 
 
 def harvest_matrix(A, hb: HarvestBuffer, *, k=8, nev=5, every=10, rows=256, seed=0, tol_star=1e-9, tol=1e-6,
-                   maxiter=5000, x0_seed=1, offset=0.0):
-    """Append one matrix's samples to hb (FP64 context for both passes)."""
+                   maxiter=5000, x0_seed=1, offset=0.0, star_offset=4.0):
+    """Append one matrix's samples to hb (FP64 context for both passes).  The
+    converged eigenvectors x* do not depend on the preconditioner that found
+    them, so the tight pass uses the faster shift (``star_offset``); the
+    harvesting pass uses the diagonal step the network is trained on
+    (``offset``)."""
     import torch
     from synth import workloads as W
     ctx = Context.from_csr(A, dtype=F64)
-    ctx.set_precond_offset(offset)
+    ctx.set_precond_offset(star_offset)
     X0 = torch.from_numpy(W.initial_block(A.n, k, seed=x0_seed)).cuda()
     Xs = X0.clone()
     r_star = ctx.solve(Xs, nev, tol=tol_star, maxiter=maxiter)
+    ctx.set_precond_offset(offset)
     xstar = Xs[:, :nev].contiguous()
     hb.set_xstar(xstar, nev=nev, seed=seed)
     hb.h.every, hb.h.rows = every, rows
