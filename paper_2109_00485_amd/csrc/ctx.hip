@@ -57,91 +57,103 @@ __global__ void strict_rowptr(int64_t n, const int64_t *__restrict__ rp, int64_t
     if (i <= n) rps[i] = rp[i] - i;
 }
 
-// One wavefront per row: split the row into its diagonal and strict part, and
-// accumulate |h| statistics of full symmetric rows (row part here, column
-// part by atomics into the partner rows).
+// One wavefront per row: split the row into its diagonal and strict part.
 template <typename T>
 __global__ void split_rows(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                            const T *__restrict__ val, int32_t *__restrict__ ci, T *__restrict__ vs,
-                           T *__restrict__ diag, double *__restrict__ absrow, int *__restrict__ cntrow) {
+                           T *__restrict__ diag) {
     int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LOBPCG_WAVE;
     int lane = threadIdx.x % LOBPCG_WAVE;
     if (i >= n) return;
     int64_t b = rp[i], e = rp[i + 1];
-    double s = 0.0;
-    int c = 0;
     for (int64_t q = b + 1 + lane; q < e; q += LOBPCG_WAVE) {
-        int32_t j = col[q];
-        T v = val[q];
         int64_t dst = q - i - 1;
-        ci[dst] = j;
-        vs[dst] = v;
-        double a = fabs((double)v);
-        s += a;
-        c += 1;
-        atomicAdd(&absrow[j], a);
-        atomicAdd(&cntrow[j], 1);
+        ci[dst] = col[q];
+        vs[dst] = val[q];
+    }
+    if (lane == 0) diag[i] = val[b];
+}
+
+// |h| statistics of the full symmetric rows from the two views of the strict
+// upper triangle (row view rp/val, column view cp/cval): one wavefront per row,
+// lane-strided sums combined by a fixed shuffle tree, so the results are the
+// same in every run.  gamma = max_i (|d_i| + sum_{j != i} |h_ij|) (a maximum:
+// any order gives the same value).
+template <typename T>
+__global__ void full_row_stats(int64_t n, const int64_t *__restrict__ rp, const T *__restrict__ val,
+                               const int64_t *__restrict__ cp, const T *__restrict__ cval, const T *__restrict__ diag,
+                               double *__restrict__ absrow, float *__restrict__ rownorm,
+                               unsigned long long *__restrict__ gmax) {
+    int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LOBPCG_WAVE;
+    int lane = threadIdx.x % LOBPCG_WAVE;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t q = rp[i] + lane; q < rp[i + 1]; q += LOBPCG_WAVE) s += fabs((double)val[q]);
+    for (int64_t q = cp[i] + lane; q < cp[i + 1]; q += LOBPCG_WAVE) s += fabs((double)cval[q]);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) {
+        absrow[i] = s;
+        rownorm[i] = (float)s;
+        const double g = s + fabs((double)diag[i]);
+        // non-negative doubles order like their bit patterns
+        atomicMax(gmax, (unsigned long long)__double_as_longlong(g));
+    }
+}
+
+// Mean |h| over the off-diagonal nonzeros of each 64-row tile-row: one
+// wavefront per tile-row, fixed shuffle tree.
+__global__ void tile_stats(int64_t n, const int64_t *__restrict__ rp, const int64_t *__restrict__ cp,
+                           const double *__restrict__ absrow, float *__restrict__ tm) {
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LOBPCG_WAVE;
+    const int lane = threadIdx.x % LOBPCG_WAVE;
+    const int64_t i = t * 64 + lane;
+    if (t * 64 >= n) return;
+    double a = 0.0;
+    int64_t c = 0;
+    if (i < n) {
+        a = absrow[i];
+        c = (rp[i + 1] - rp[i]) + (cp[i + 1] - cp[i]);
     }
     for (int off = 32; off > 0; off >>= 1) {
-        s += __shfl_xor(s, off);
+        a += __shfl_xor(a, off);
         c += __shfl_xor(c, off);
     }
-    if (lane == 0) {
-        diag[i] = val[b];
-        atomicAdd(&absrow[i], s);
-        atomicAdd(&cntrow[i], c);
-    }
-}
-
-// gamma = max_i (|d_i| + sum_{j != i} |h_ij|); rownorm feature; tile sums.
-template <typename T>
-__global__ void row_stats(int64_t n, const T *__restrict__ diag, const double *__restrict__ absrow,
-                          const int *__restrict__ cntrow, float *__restrict__ rownorm,
-                          unsigned long long *__restrict__ gmax, double *__restrict__ tile_abs,
-                          int *__restrict__ tile_cnt) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double a = absrow[i];
-    rownorm[i] = (float)a;
-    double g = a + fabs((double)diag[i]);
-    // non-negative doubles order like their bit patterns
-    atomicMax(gmax, (unsigned long long)__double_as_longlong(g));
-    atomicAdd(&tile_abs[i / 64], a);
-    atomicAdd(&tile_cnt[i / 64], cntrow[i]);
-}
-
-__global__ void tile_mean(int64_t n, const double *__restrict__ tile_abs, const int *__restrict__ tile_cnt,
-                          float *__restrict__ tm) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int c = tile_cnt[i / 64];
-    tm[i] = c > 0 ? (float)(tile_abs[i / 64] / (double)c) : 0.0f;
+    if (i < n) tm[i] = c > 0 ? (float)(a / (double)c) : 0.0f;
 }
 
 template <typename T>
 int build_csr(lobpcg_ctx *ctx, const int64_t *rp, const int32_t *col, const void *valv, hipStream_t s) {
     const T *val = (const T *)valv;
     const int64_t n = ctx->n;
-    int64_t ntile = (n + 63) / 64;
-    double *absrow = nullptr, *tile_abs = nullptr;
-    int *cntrow = nullptr, *tile_cnt = nullptr;
-    unsigned long long *gmax = nullptr;
-    HIP_TRY(ctx, hipMallocAsync((void **)&absrow, n * sizeof(double), s));
-    HIP_TRY(ctx, hipMallocAsync((void **)&cntrow, n * sizeof(int), s));
-    HIP_TRY(ctx, hipMallocAsync((void **)&tile_abs, ntile * sizeof(double), s));
-    HIP_TRY(ctx, hipMallocAsync((void **)&tile_cnt, ntile * sizeof(int), s));
-    HIP_TRY(ctx, hipMallocAsync((void **)&gmax, sizeof(unsigned long long), s));
-    HIP_TRY(ctx, hipMemsetAsync(absrow, 0, n * sizeof(double), s));
-    HIP_TRY(ctx, hipMemsetAsync(cntrow, 0, n * sizeof(int), s));
-    HIP_TRY(ctx, hipMemsetAsync(tile_abs, 0, ntile * sizeof(double), s));
-    HIP_TRY(ctx, hipMemsetAsync(tile_cnt, 0, ntile * sizeof(int), s));
-    HIP_TRY(ctx, hipMemsetAsync(gmax, 0, sizeof(unsigned long long), s));
     strict_rowptr<<<ceil_div(n + 1, 256), 256, 0, s>>>(n, rp, ctx->rp);
     split_rows<T><<<ceil_div(n * LOBPCG_WAVE, 256), 256, 0, s>>>(n, rp, col, val, ctx->ci, (T *)ctx->val,
-                                                                 (T *)ctx->diag, absrow, cntrow);
-    row_stats<T><<<ceil_div(n, 256), 256, 0, s>>>(n, (const T *)ctx->diag, absrow, cntrow, ctx->feat_rownorm,
-                                                  gmax, tile_abs, tile_cnt);
-    tile_mean<<<ceil_div(n, 256), 256, 0, s>>>(n, tile_abs, tile_cnt, ctx->feat_tilemean);
+                                                                 (T *)ctx->diag);
+    HIP_TRY(ctx, hipGetLastError());
+    return LOBPCG_OK;
+}
+
+}  // namespace
+
+// gamma and the per-row network features, once both views of the strict upper
+// triangle exist (called by the column-view build)
+int build_row_stats(lobpcg_ctx *ctx, hipStream_t s) {
+    const int64_t n = ctx->n;
+    double *absrow = nullptr;
+    unsigned long long *gmax = nullptr;
+    HIP_TRY(ctx, hipMallocAsync((void **)&absrow, n * sizeof(double), s));
+    HIP_TRY(ctx, hipMallocAsync((void **)&gmax, sizeof(unsigned long long), s));
+    HIP_TRY(ctx, hipMemsetAsync(gmax, 0, sizeof(unsigned long long), s));
+    const int grid = ceil_div(n * LOBPCG_WAVE, 256);
+    if (ctx->dtype == LOBPCG_F32)
+        full_row_stats<float><<<grid, 256, 0, s>>>(n, ctx->rp, (const float *)ctx->val, ctx->cp,
+                                                   (const float *)ctx->cval, (const float *)ctx->diag, absrow,
+                                                   ctx->feat_rownorm, gmax);
+    else
+        full_row_stats<double><<<grid, 256, 0, s>>>(n, ctx->rp, (const double *)ctx->val, ctx->cp,
+                                                    (const double *)ctx->cval, (const double *)ctx->diag, absrow,
+                                                    ctx->feat_rownorm, gmax);
+    tile_stats<<<ceil_div(((n + 63) / 64) * LOBPCG_WAVE, 256), 256, 0, s>>>(n, ctx->rp, ctx->cp, absrow,
+                                                                             ctx->feat_tilemean);
     unsigned long long g = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&g, gmax, sizeof g, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -149,13 +161,12 @@ int build_csr(lobpcg_ctx *ctx, const int64_t *rp, const int32_t *col, const void
     double gd;
     memcpy(&gd, &g, sizeof gd);
     ctx->gamma = gd;
-    hipFreeAsync(absrow, s);
-    hipFreeAsync(cntrow, s);
-    hipFreeAsync(tile_abs, s);
-    hipFreeAsync(tile_cnt, s);
-    hipFreeAsync(gmax, s);
+    (void)hipFreeAsync(absrow, s);
+    (void)hipFreeAsync(gmax, s);
     return LOBPCG_OK;
 }
+
+namespace {
 
 void free_ctx(lobpcg_ctx *c) {
     if (!c) return;

@@ -167,3 +167,5 @@ int mlp_precond_ready(lobpcg_ctx *ctx);
 int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s);
 // one harvest snapshot after iteration `it` of a solve (X, HX, rr_theta current)
 int harvest_snapshot(lobpcg_ctx *ctx, int k, lobpcg_harvest *h, hipStream_t s);
+// gamma and the per-row network features from both views of the strict upper triangle
+int build_row_stats(lobpcg_ctx *ctx, hipStream_t s);

@@ -531,6 +531,10 @@ int build_csc(lobpcg_ctx *ctx, hipStream_t s) {
         HIP_TRY(ctx, hipMemcpyAsync(ctx->cri, ri.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipMemcpyAsync(ctx->cval, cv.data(), m * sizeof(T), hipMemcpyHostToDevice, s));
     }
+    {
+        const int rc = build_row_stats(ctx, s);   // before the tiled format pads the value arrays
+        if (rc != LOBPCG_OK) return rc;
+    }
     // long rows for spmm_heavy_kernel
     std::vector<int32_t> heavy;
     for (int64_t i = 0; i < n; ++i)

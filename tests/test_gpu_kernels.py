@@ -177,6 +177,40 @@ def test_gershgorin_matches_oracle():
     assert np.array_equal(d, A.diag)
 
 
+@pytest.mark.parametrize("fmt", ["csr", "tiled"])
+def test_row_statistics_deterministic(fmt):
+    """gamma and the per-row network features (full-row off-diagonal 1-norm,
+    mean |h| of the row's 64-row tile) are the same bits in every context and
+    match the oracle's definitions (a power-law pattern, hubs included, and a
+    ragged last tile)."""
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    if fmt == "csr":
+        A = synth.zipf(20000 + 37, lmin=4, lmax=3000, seed=11, f32=False)
+    else:
+        A = synth.tiled(64 * 60, tile=64, tile_draws=5, p=0.1, seed=2)
+    H = oracle.SymMatrix.from_csr(A)
+    f = {"csr": L.FORMAT_CSR, "tiled": L.FORMAT_TILED}[fmt]
+    runs = []
+    for _ in range(3):
+        ctx = upload(A, False, fmt=f)
+        rho, tm = (x.cpu().numpy() for x in ctx.features())
+        runs.append((ctx.query()["gamma"], rho, tm))
+        ctx.close()
+    for g, rho, tm in runs[1:]:
+        assert g == runs[0][0] and np.array_equal(rho, runs[0][1]) and np.array_equal(tm, runs[0][2])
+    g, rho, tm = runs[0]
+    assert g == pytest.approx(H.gershgorin(), rel=1e-13)
+    off = H.row_offdiag_abs()
+    np.testing.assert_allclose(rho, off.astype(np.float32), rtol=1e-6)
+    cnt = H.row_offdiag_count().astype(np.float64)
+    nt = (A.n + 63) // 64
+    pad = nt * 64 - A.n
+    tile_mean = (np.concatenate([off, np.zeros(pad)]).reshape(nt, 64).sum(1) /
+                 np.maximum(np.concatenate([cnt, np.zeros(pad)]).reshape(nt, 64).sum(1), 1))
+    np.testing.assert_allclose(tm, np.repeat(tile_mean, 64)[:A.n].astype(np.float32), rtol=1e-6)
+
+
 def test_create_rejects_malformed():
     import paper_2109_00485_amd as L
     torch = torch_cuda()
