@@ -83,6 +83,22 @@ def test_random_sym_20k(f32):
     assert r.confirmations >= 1
 
 
+@pytest.mark.parametrize("f32", [False, True])
+def test_tiled_format_solve_ragged(f32):
+    """The tiled format (16-bit local codes, staged X blocks) inside a full
+    solve, on n = 1000 (the last tile-row holds 40 rows), against the oracle."""
+    import paper_2109_00485_amd as L
+    A = W.make_matrix("random_sym_1k")
+    H, ref = oracle_solve("rs1k", A)
+    ctx = upload(A, f32, fmt=L.FORMAT_TILED)
+    assert ctx.query()["format"] == L.FORMAT_TILED
+    dt = np.float32 if f32 else np.float64
+    X = to_dev(W.initial_block(A.n, 8, seed=1), dt)
+    r = ctx.solve(X, 5, maxiter=3000, tol=3e-6 if f32 else 1e-6)
+    assert r.status == 0, r
+    check_against_oracle(H, ref, r, X.cpu().numpy().astype(np.float64), f32)
+
+
 @pytest.mark.parametrize("k,nev", [(3, 2), (5, 3), (16, 5)])
 def test_block_sizes_against_dense_spectrum(k, nev):
     """Odd and largest Rayleigh-Ritz pencils (3k = 9, 15 and 48; an odd order
