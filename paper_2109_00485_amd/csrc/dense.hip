@@ -45,7 +45,10 @@ __device__ inline double wave_sum(double v) {
 }
 
 // In-place lower Cholesky of the N x N matrix a (row-major, leading dim LD).
-// Returns false if a pivot falls below tol.  Any workgroup size.
+// Returns false if a pivot falls below tol.  Any workgroup size.  Right-looking:
+// after column j is scaled, every thread subtracts its share of the rank-1
+// update from the trailing lower triangle, so no thread runs a long dependent
+// dot product; each entry still receives its updates in the order p = 0, 1, ...
 __device__ bool chol_lower(double *a, int N, double tol) {
     const int t = threadIdx.x;
     __shared__ int bad;
@@ -53,17 +56,18 @@ __device__ bool chol_lower(double *a, int N, double tol) {
     __syncthreads();
     for (int j = 0; j < N; ++j) {
         if (t == 0) {
-            double d = a[j * LD + j];
-            for (int p = 0; p < j; ++p) d -= a[j * LD + p] * a[j * LD + p];
+            const double d = a[j * LD + j];
             if (!(d > tol)) bad = 1;
             a[j * LD + j] = d > 0 ? sqrt(d) : 1.0;
         }
         __syncthreads();
         const double piv = a[j * LD + j];
-        for (int i = j + 1 + t; i < N; i += blockDim.x) {
-            double v = a[i * LD + j];
-            for (int p = 0; p < j; ++p) v -= a[i * LD + p] * a[j * LD + p];
-            a[i * LD + j] = v / piv;
+        for (int i = j + 1 + t; i < N; i += blockDim.x) a[i * LD + j] /= piv;
+        __syncthreads();
+        const int m = N - j - 1;
+        for (int e = t; e < m * m; e += blockDim.x) {
+            const int i = j + 1 + e / m, l = j + 1 + e % m;
+            if (l <= i) a[i * LD + l] -= a[i * LD + j] * a[l * LD + j];
         }
         __syncthreads();
     }
