@@ -116,7 +116,7 @@ def learned_vs_diag(args):
     return out
 
 
-def cpu_baseline(A, k, budget_s=15.0):
+def cpu_baseline(A, k, budget_s=15.0, iters_sample=6):
     import oracle
     from synth import workloads as W
     t0 = time.time()
@@ -137,9 +137,19 @@ def cpu_baseline(A, k, budget_s=15.0):
     if omp:
         cores = min(cores, int(omp))
     gbs = algorithmic_bytes(A.n, A.nnz, k) / per / 1e9
+    # a few iterations of the oracle's FP64 LOBPCG on the same matrix and start:
+    # seconds per iteration (the start-up Rayleigh-Ritz excluded)
+    from oracle.lobpcg import lobpcg as oracle_lobpcg
+    marks = []
+    oracle_lobpcg(H, X, 5, tol=1e-6, maxiter=iters_sample, d=A.diag,
+                  callback=lambda it, *a: marks.append(time.perf_counter()))
+    t_end = time.perf_counter()
+    per_iter = (t_end - marks[0]) / max(len(marks), 1) if marks else None
     return dict(value=round(gbs, 3), unit="GB/s", cores=cores, kind="oracle",
                 sample=f"{len(times)} FP64 oracle sparse products (two-pass, OpenMP) of the full matrix, "
-                       f"median {per * 1e3:.1f} ms each")
+                       f"median {per * 1e3:.1f} ms each; {len(marks)} iterations of the FP64 oracle LOBPCG "
+                       f"(diagonal step, shift at theta_j) from the bench's start",
+                solve_s_per_iteration=None if per_iter is None else round(per_iter, 3))
 
 
 def main():
@@ -365,7 +375,13 @@ def main():
             out["learned_vs_diag"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         try:
-            out["cpu_baseline"] = cpu_baseline(A, args.k)
+            cb = cpu_baseline(A, args.k)
+            if cb.get("solve_s_per_iteration"):
+                # the oracle's cost per iteration times the GPU solve's iteration count
+                est = cb["solve_s_per_iteration"] * last.iters
+                cb["solve_s_estimate"] = round(est, 1)
+                cb["gpu_solve_speedup_estimate"] = round(est / (ms_per_step / 1e3), 1)
+            out["cpu_baseline"] = cb
         except Exception as e:  # the GPU figure stands on its own
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
