@@ -214,6 +214,17 @@ __global__ __launch_bounds__(HEAVY_THREADS) void spmm_heavy_kernel(
 #ifndef LOBPCG_TW_CHUNK
 #define LOBPCG_TW_CHUNK 4       // entries a lane takes per step (4 or 8)
 #endif
+#ifndef LOBPCG_TW_PF
+#define LOBPCG_TW_PF 1          // prefetch the next chunk of each lane (full-width path)
+#endif
+#ifndef LOBPCG_TW_MINWAVES
+#define LOBPCG_TW_MINWAVES 6    // ask the register allocator for this many waves per SIMD (0: its choice)
+#endif
+#if LOBPCG_TW_MINWAVES > 0
+#define TW_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(LOBPCG_TW_MINWAVES)))
+#else
+#define TW_WAVES_ATTR
+#endif
 #ifndef LOBPCG_TW_PAD
 #define LOBPCG_TW_PAD -1        // pad staged X rows by 16 bytes (-1: by block width)
 #endif
@@ -228,6 +239,8 @@ struct TwShape {
     static constexpr int THREADS = 64 * TG;
     // entries per chunk (segments are padded to 8, so 8 or 4)
     static constexpr int CH = LOBPCG_TW_CHUNK;
+    // keep the lane's next chunk in flight while it works on the current one
+    static constexpr bool PF = LOBPCG_TW_PF;
     static constexpr int PAD = (LOBPCG_TW_PAD < 0 ? !NARROW : LOBPCG_TW_PAD) ? 16 / (int)sizeof(T) : 0;
     static constexpr int STRIDE = KP + PAD;
     static constexpr int SLOT = 64 * STRIDE;           // elements per staged 64-row block
@@ -251,8 +264,12 @@ __device__ inline void tw_unit(int idx, int &s, int &rr, int &q) {
     q = (rem - rr * UPR) * VEC;
 }
 
-template <typename T, int KP>
-__global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
+// FULL: k equals the compiled width KP (a whole number of 16-byte units), so
+// staging is vectorised and each entry's update has no per-column branches.
+// Each lane walks its chunks of CH entries with the next chunk's codes and
+// values already in flight.
+template <typename T, int KP, bool FULL>
+__global__ __launch_bounds__((TwShape<T, KP>::THREADS)) TW_WAVES_ATTR void spmm_tiled_kernel(
     int64_t n, int k, const int64_t *__restrict__ rp, const uint16_t *__restrict__ rix, const T *__restrict__ rv,
     const int64_t *__restrict__ cp, const uint16_t *__restrict__ cix, const T *__restrict__ cv,
     const int32_t *__restrict__ rlist_off, const int32_t *__restrict__ rlist,
@@ -268,7 +285,7 @@ __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
     const int r = threadIdx.x / TG, sl = threadIdx.x % TG;
     const int64_t i = I * 64 + r;
     const bool valid = i < n;
-    const bool vec = (k % VEC) == 0 && k == KP;
+    constexpr bool vec = FULL;
     T acc[KP];
 #pragma unroll
     for (int q = 0; q < KP; ++q) acc[q] = T(0);
@@ -280,6 +297,39 @@ __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
             const int64_t grow = (int64_t)s_list[s0 + s] * 64 + rr;
             Xs[(b * S::WT + s) * S::SLOT + rr * S::STRIDE + q] = grow < n ? X[grow * k + q] : T(0);
         }
+    };
+    // one lane's chunk of CH entries in registers: CH 16-bit codes and CH values
+    constexpr int CH = S::CH;
+    using CodeT = typename std::conditional<CH == 8, uint4, uint2>::type;
+    struct Chunk {
+        CodeT c;
+        V a[CH * (int)sizeof(T) / 16];
+    };
+    auto load_chunk = [&](const uint16_t *ix, const T *vals, int64_t p) {
+        Chunk ck;
+        ck.c = *reinterpret_cast<const CodeT *>(ix + p);
+#pragma unroll
+        for (int h = 0; h < CH * (int)sizeof(T) / 16; ++h) ck.a[h] = *reinterpret_cast<const V *>(vals + p + h * VEC);
+        return ck;
+    };
+    auto pick_chunk = [&](bool first, const Chunk &a, const Chunk &b) {   // element-wise select
+        Chunk ck;
+        ck.c.x = first ? a.c.x : b.c.x;
+        ck.c.y = first ? a.c.y : b.c.y;
+        if constexpr (CH == 8) {
+            ck.c.z = first ? a.c.z : b.c.z;
+            ck.c.w = first ? a.c.w : b.c.w;
+        }
+#pragma unroll
+        for (int h = 0; h < CH * (int)sizeof(T) / 16; ++h) {
+            ck.a[h].x = first ? a.a[h].x : b.a[h].x;
+            ck.a[h].y = first ? a.a[h].y : b.a[h].y;
+            if constexpr (sizeof(T) == 4) {
+                ck.a[h].z = first ? a.a[h].z : b.a[h].z;
+                ck.a[h].w = first ? a.a[h].w : b.a[h].w;
+            }
+        }
+        return ck;
     };
     V pre[S::MAXV];
     auto fetch = [&](int s0, int s1) {   // global loads of a window into registers
@@ -321,6 +371,17 @@ __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
             pos = ptr[i] + S::CH * sl;
             seg_end = ptr[i + 1];
         }
+        // with prefetch, cur holds the chunk at pos and nxt the lane's following one
+        // (segments are padded to 8 entries, so a chunk that starts inside one ends inside it)
+        constexpr bool PF = FULL && S::PF;
+        Chunk cur{}, nxt{};
+        if constexpr (PF) {
+            if (pos < seg_end) {
+                cur = load_chunk(ix, vals, pos);
+                // past the segment's end the load is redirected to its last chunk (never used)
+                nxt = load_chunk(ix, vals, min(pos + CH * TG, seg_end - CH));
+            }
+        }
         __syncthreads();
         if (nslots > 0) {
             if (vec) {
@@ -339,30 +400,28 @@ __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
             if (NBUF == 2 && vec && n0 < n1) fetch(n0, n1);   // next window in flight during this one
             bool more = pos < seg_end;
             while (more) {
-                constexpr int CH = S::CH;
+                Chunk ck;
+                if constexpr (PF) ck = cur;
+                else ck = load_chunk(ix, vals, pos);
                 unsigned u[CH];
                 if constexpr (CH == 8) {
-                    const uint4 uu = *reinterpret_cast<const uint4 *>(ix + pos);
-                    const unsigned w4[4] = {uu.x, uu.y, uu.z, uu.w};
+                    const unsigned w4[4] = {ck.c.x, ck.c.y, ck.c.z, ck.c.w};
 #pragma unroll
                     for (int h = 0; h < 4; ++h) { u[2 * h] = w4[h] & 0xFFFFu; u[2 * h + 1] = w4[h] >> 16; }
                 } else {
-                    const uint2 uu = *reinterpret_cast<const uint2 *>(ix + pos);
-                    u[0] = uu.x & 0xFFFFu; u[1] = uu.x >> 16; u[2] = uu.y & 0xFFFFu; u[3] = uu.y >> 16;
+                    u[0] = ck.c.x & 0xFFFFu; u[1] = ck.c.x >> 16; u[2] = ck.c.y & 0xFFFFu; u[3] = ck.c.y >> 16;
                 }
                 T v[CH];
                 if constexpr (sizeof(T) == 4) {
 #pragma unroll
                     for (int h = 0; h < CH / 4; ++h) {
-                        const float4 a = *reinterpret_cast<const float4 *>(vals + pos + 4 * h);
-                        v[4 * h] = a.x; v[4 * h + 1] = a.y; v[4 * h + 2] = a.z; v[4 * h + 3] = a.w;
+                        v[4 * h] = ck.a[h].x; v[4 * h + 1] = ck.a[h].y; v[4 * h + 2] = ck.a[h].z; v[4 * h + 3] = ck.a[h].w;
                     }
                 } else {
 #pragma unroll
                     for (int h = 0; h < CH / 2; ++h) {
-                        const double2 a = *reinterpret_cast<const double2 *>(vals + pos + 2 * h);
-                        v[2 * h] = a.x;
-                        v[2 * h + 1] = a.y;
+                        v[2 * h] = ck.a[h].x;
+                        v[2 * h + 1] = ck.a[h].y;
                     }
                 }
                 // the code slot*64 + c is the staged row index; rows of this window
@@ -372,11 +431,30 @@ __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) void spmm_tiled_kernel(
                 int nb = 0;
 #pragma unroll
                 for (int t = 0; t < CH; ++t) nb += u[t] < lim ? 1 : 0;
+                // FULL: the width is a compile-time constant, so each entry is one
+                // straight run of 16-byte LDS reads and FMAs
 #pragma unroll
                 for (int t = 0; t < CH; ++t)
-                    if (t >= off && t < nb) axpy_row<T, KP>(acc, v[t], xb + (u[t] - base) * S::STRIDE, k);
+                    if (t >= off && t < nb) axpy_row<T, KP>(acc, v[t], xb + (u[t] - base) * S::STRIDE, FULL ? KP : k);
                 off = nb;   // slots are sorted within the chunk: [old off, nb) was just consumed
-                if (off == CH) {
+                if constexpr (PF) {
+                    // every active lane reloads nxt (no load under a branch, so the loaded
+                    // registers need no copy and the load stays in flight through the next
+                    // chunk): the chunk after the next one when this chunk is done, else
+                    // the next one again
+                    const bool adv = off == CH;
+                    const int64_t npos = pos + CH * TG;
+                    const int64_t want = adv ? npos + CH * TG : npos;
+                    cur = pick_chunk(adv, nxt, cur);
+                    nxt = load_chunk(ix, vals, min(want, seg_end - CH));
+                    if (adv) {
+                        pos = npos;
+                        off = 0;
+                        more = pos < seg_end;
+                    } else {
+                        more = false;
+                    }
+                } else if (off == CH) {
                     pos += CH * TG;
                     off = 0;
                     more = pos < seg_end;
@@ -452,12 +530,20 @@ int spmm_pull(lobpcg_ctx *ctx, const T *X, T *Y, int k, hipStream_t s) {
         const T *rv = (const T *)ctx->val, *cv = (const T *)ctx->cval, *diag = (const T *)ctx->diag;
 #define TW_ARGS ctx->n, k, ctx->rp, tf.rix, rv, ctx->cp, tf.cix, cv, tf.rlist_off, tf.rlist, tf.clist_off, tf.clist, \
                 diag, X, Y
+#define TW_LAUNCH(KP)                                                                        \
+    do {                                                                                     \
+        if (k == (KP) && (KP) % TwShape<T, KP>::VEC == 0)                                    \
+            spmm_tiled_kernel<T, KP, true><<<grid, TwShape<T, KP>::THREADS, 0, s>>>(TW_ARGS);  \
+        else                                                                                 \
+            spmm_tiled_kernel<T, KP, false><<<grid, TwShape<T, KP>::THREADS, 0, s>>>(TW_ARGS); \
+    } while (0)
         if (k <= 4)
-            spmm_tiled_kernel<T, 4><<<grid, TwShape<T, 4>::THREADS, 0, s>>>(TW_ARGS);
+            TW_LAUNCH(4);
         else if (k <= 8)
-            spmm_tiled_kernel<T, 8><<<grid, TwShape<T, 8>::THREADS, 0, s>>>(TW_ARGS);
+            TW_LAUNCH(8);
         else
-            spmm_tiled_kernel<T, 16><<<grid, TwShape<T, 16>::THREADS, 0, s>>>(TW_ARGS);
+            TW_LAUNCH(16);
+#undef TW_LAUNCH
 #undef TW_ARGS
     } else {
         spmm_pull_launch<T, false>(ctx, X, Y, k, s);

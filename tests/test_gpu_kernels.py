@@ -39,7 +39,7 @@ MATRICES = {
 
 
 @pytest.mark.parametrize("name", list(MATRICES))
-@pytest.mark.parametrize("k", [1, 5, 8, 16])
+@pytest.mark.parametrize("k", [1, 4, 5, 8, 16])
 @pytest.mark.parametrize("f32", [True, False])
 @pytest.mark.parametrize("fmt", ["csr", "tiled"])
 def test_spmm_parity(name, k, f32, fmt):
@@ -57,7 +57,7 @@ def test_spmm_parity(name, k, f32, fmt):
     assert err <= (1e-5 if f32 else 1e-12), err
 
 
-@pytest.mark.parametrize("k", [1, 8, 16])
+@pytest.mark.parametrize("k", [1, 4, 8, 16])
 @pytest.mark.parametrize("fmt", ["csr", "tiled"])
 @pytest.mark.parametrize("hubs", [False, True])
 def test_spmm_integer_bitwise(k, fmt, hubs):
