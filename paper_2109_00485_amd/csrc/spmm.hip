@@ -158,16 +158,6 @@ __global__ __launch_bounds__(SPMM_THREADS) void spmm_pull_kernel(
         if (q < k && (q % GROUP) == sl) yi[q] = acc[q] + di * xi[q];
 }
 
-// Tiled format: one 512-thread workgroup per 64-row tile-row (8 lanes per
-// row).  Both traversals walk the tile-row's slot lists in windows of WT slots:
-// the workgroup stages the 64-row blocks of X that the window's slots refer to
-// into LDS with coalesced 16-byte loads (each X block is fetched once per
-// tile-row, not once per entry), then each lane consumes its entries whose
-// slot falls in the window.  Row segments are padded to whole 8-entry chunks;
-// chunk m of a segment belongs to lane m % 8, which reads it with one 16-byte
-// index load and two 16-byte value loads; a chunk that straddles a window
-// boundary is read again (from cache) in the next window.  Entries are sorted
-// by slot, so what a lane consumes of a chunk is always a contiguous run.
 // One workgroup per long CSR row (both segments longer than HEAVY_ROW in
 // total): the threads stride over the row's entries, each keeps k partial
 // sums, and a fixed-order block reduction writes Y_i.
@@ -264,10 +254,20 @@ __device__ inline void tw_unit(int idx, int &s, int &rr, int &q) {
     q = (rem - rr * UPR) * VEC;
 }
 
+// Tiled format: one 512-thread workgroup per 64-row tile-row (8 lanes per
+// row).  Both traversals walk the tile-row's slot lists in windows of WT slots:
+// the workgroup stages the 64-row blocks of X that the window's slots refer to
+// into LDS with coalesced 16-byte loads (each X block is fetched once per
+// tile-row, not once per entry), then each lane consumes its entries whose
+// slot falls in the window.  Row segments are padded to whole 8-entry chunks;
+// chunk m (CH entries) of a segment belongs to lane m % 8, which reads its
+// codes and values with one load each; a chunk that straddles a window
+// boundary is consumed in two windows.  Entries are sorted by slot, so what a
+// lane consumes of a chunk is always a contiguous run.
 // FULL: k equals the compiled width KP (a whole number of 16-byte units), so
-// staging is vectorised and each entry's update has no per-column branches.
-// Each lane walks its chunks of CH entries with the next chunk's codes and
-// values already in flight.
+// staging is vectorised and each entry's update has no per-column branches,
+// and each lane keeps its next chunk's loads in flight while it works on the
+// current one.
 template <typename T, int KP, bool FULL>
 __global__ __launch_bounds__((TwShape<T, KP>::THREADS)) TW_WAVES_ATTR void spmm_tiled_kernel(
     int64_t n, int k, const int64_t *__restrict__ rp, const uint16_t *__restrict__ rix, const T *__restrict__ rv,
