@@ -234,8 +234,9 @@ struct TwShape {
     static constexpr int PAD = (LOBPCG_TW_PAD < 0 ? !NARROW : LOBPCG_TW_PAD) ? 16 / (int)sizeof(T) : 0;
     static constexpr int STRIDE = KP + PAD;
     static constexpr int SLOT = 64 * STRIDE;           // elements per staged 64-row block
-    // 32 KB of staged X for k <= 8 (four workgroups per CU), 64 KB for wider blocks
-    static constexpr int LDS_BYTES = LOBPCG_TW_LDS ? LOBPCG_TW_LDS : (KP * (int)sizeof(T) > 32 ? 65536 : 32768);
+    // staged X: 40 KB (20 slots of 32-byte rows) for rows of up to 32 bytes, so
+    // three workgroups share a CU; 64 KB for wider rows (measured best on gfx950)
+    static constexpr int LDS_BYTES = LOBPCG_TW_LDS ? LOBPCG_TW_LDS : (KP * (int)sizeof(T) > 32 ? 65536 : 40960);
     static constexpr int WT0 = LDS_BYTES / NBUF / (SLOT * (int)sizeof(T));
     static constexpr int WT = WT0 < 2 ? 2 : WT0;       // slots per window
     static constexpr int VEC = 16 / (int)sizeof(T);    // elements per 16-byte load
