@@ -132,11 +132,16 @@ def cpu_baseline(A, k, budget_s=15.0, iters_sample=6):
         if time.time() - t_start > budget_s or len(times) >= 20:
             break
     per = float(np.median(times))
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    omp = os.environ.get("OMP_NUM_THREADS")
-    if omp:
-        cores = min(cores, int(omp))
+    cores = oracle.threads()
     gbs = algorithmic_bytes(A.n, A.nnz, k) / per / 1e9
+    # the same product on one thread
+    oracle.set_threads(1)
+    try:
+        t = time.perf_counter()
+        H @ X
+        per1 = time.perf_counter() - t
+    finally:
+        oracle.set_threads(cores)
     # a few iterations of the oracle's FP64 LOBPCG on the same matrix and start:
     # seconds per iteration (the start-up Rayleigh-Ritz excluded)
     from oracle.lobpcg import lobpcg as oracle_lobpcg
@@ -149,6 +154,7 @@ def cpu_baseline(A, k, budget_s=15.0, iters_sample=6):
                 sample=f"{len(times)} FP64 oracle sparse products (two-pass, OpenMP) of the full matrix, "
                        f"median {per * 1e3:.1f} ms each; {len(marks)} iterations of the FP64 oracle LOBPCG "
                        f"(diagonal step, shift at theta_j) from the bench's start",
+                single_thread_value=round(algorithmic_bytes(A.n, A.nnz, k) / per1 / 1e9, 3),
                 solve_s_per_iteration=None if per_iter is None else round(per_iter, 3))
 
 

@@ -63,8 +63,22 @@ def _load():
     lib.oracle_row_offdiag_abs.argtypes = [P, P]
     lib.oracle_row_offdiag_count.restype = None
     lib.oracle_row_offdiag_count.argtypes = [P, P]
+    lib.oracle_set_threads.restype = None
+    lib.oracle_set_threads.argtypes = [cint]
+    lib.oracle_get_threads.restype = cint
+    lib.oracle_get_threads.argtypes = []
     _lib = lib
     return lib
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().oracle_get_threads())
+
+
+def set_threads(t: int) -> None:
+    """Set the threads of the oracle's OpenMP loops (baseline timing only)."""
+    _load().oracle_set_threads(int(t))
 
 
 class SymMatrix:

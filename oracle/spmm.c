@@ -19,6 +19,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 typedef struct {
     int64_t n, nnz;
@@ -143,3 +144,7 @@ void oracle_row_offdiag_count(const oracle_mat *m, int64_t *out) {
         out[i] = c + (m->cp[i + 1] - m->cp[i]);
     }
 }
+
+/* Thread count of the OpenMP loops above (timing of the CPU baseline only). */
+void oracle_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }

@@ -109,3 +109,21 @@ def test_generator_shapes():
             seg = A.col[A.row_ptr[i]:A.row_ptr[i + 1]]
             assert (np.diff(seg) > 0).all()
         assert np.all(np.diff(A.diag) >= 0)
+
+
+def test_thread_count_does_not_change_result():
+    """Both passes pull into their own output rows, so the product is the same
+    bits on one thread and on all of them."""
+    A = synth.random_sym(20000, 30, seed=11)
+    H = oracle.SymMatrix.from_csr(A)
+    X = np.random.default_rng(4).standard_normal((A.n, 5))
+    full = oracle.threads()
+    Y = H @ X
+    oracle.set_threads(1)
+    try:
+        assert oracle.threads() == 1
+        Y1 = H @ X
+    finally:
+        oracle.set_threads(full)
+    assert oracle.threads() == full
+    assert np.array_equal(Y, Y1)
