@@ -176,3 +176,87 @@ def test_bounded_scale():
     assert np.all(r >= np.exp(-2.0) * (1 - 1e-12)) and np.all(r <= np.exp(2.0) * (1 + 1e-12))
     assert r.max() > 5.0 and r.min() < 0.2        # the bound is actually reached here
     assert np.allclose(mlp.bound([0.0, 1e9, -1e9]), [0.0, 2.0, -2.0])
+
+
+def test_group_loss_hand_computed_with_span_x():
+    """Two groups of three rows, k = 1, X != 0, and a zero output layer (so the
+    learned factor is exp(0) = 1 and u = U).  Worked by hand from the loss's
+    definition:
+      group 0: w = (2, 1, 1), x = (1, 0, 1), U = (1, 2, 3), T = (1, 1, -1)
+               a = sum w x u = 2 + 0 + 3 = 5,  u' = u - x a = (-4, 2, -2)
+               sum w u' T = -8 + 2 + 2 = -4,  sum w u'^2 = 32 + 4 + 4 = 40,
+               sum w T^2 = 4,  L_0 = 1 - 16 / 160 = 9/10
+      group 1: w = (1/2, 1, 2), x = (2, -1, 0), U = (1, 0, 1), T = (0, 2, 1)
+               a = 1 + 0 + 0 = 1,  u' = (-1, 1, 1)
+               sum w u' T = 0 + 2 + 2 = 4,  sum w u'^2 = 1/2 + 1 + 2 = 7/2,
+               sum w T^2 = 0 + 4 + 2 = 6,  L_1 = 1 - 16 / 21 = 5/21
+      loss = (9/10 + 5/21) / 2 = 239/420.
+    A projection coefficient without the weights (a_0 = 4) or summed over both
+    groups (a = 6) gives another value."""
+    p = mlp.init_params(0)            # w3 = 0, b3 = 0: zero output
+    feat = np.zeros((6, 4))
+    U = np.array([1.0, 2.0, 3.0, 1.0, 0.0, 1.0])
+    T = np.array([1.0, 1.0, -1.0, 0.0, 2.0, 1.0])
+    w = np.array([2.0, 1.0, 1.0, 0.5, 1.0, 2.0])
+    X = np.array([[1.0], [0.0], [1.0], [2.0], [-1.0], [0.0]])
+    gid = np.array([0, 0, 0, 1, 1, 1])
+    L, _ = mlp.group_loss(p, feat, U, T, w, X, gid, 2, with_grad=False)
+    assert L == pytest.approx(239.0 / 420.0, rel=1e-14)
+    # each group alone
+    L0, _ = mlp.group_loss(p, feat[:3], U[:3], T[:3], w[:3], X[:3], np.zeros(3, dtype=int), 1, with_grad=False)
+    L1, _ = mlp.group_loss(p, feat[3:], U[3:], T[3:], w[3:], X[3:], np.zeros(3, dtype=int), 1, with_grad=False)
+    assert L0 == pytest.approx(0.9, rel=1e-14) and L1 == pytest.approx(5.0 / 21.0, rel=1e-14)
+
+
+def test_group_loss_target_in_span_x_is_orthogonal():
+    """With X orthonormal in the group's weighted inner product (X^T diag(w) X = I),
+    the projected direction u' = u - X (X^T diag(w) u) is w-orthogonal to span(X);
+    a target T inside span(X) therefore has cosine 0 with u' and the group's loss
+    is exactly 1, whatever u.  A projection without the weights leaves a component
+    along T."""
+    rng = np.random.default_rng(11)
+    N, k = 40, 3
+    w = rng.uniform(0.5, 2.0, N)
+    A = rng.standard_normal((N, k))
+    # weighted Gram-Schmidt via the Cholesky factor of A^T W A
+    Lc = np.linalg.cholesky(A.T @ (w[:, None] * A))
+    X = np.linalg.solve(Lc, A.T).T
+    assert np.allclose(X.T @ (w[:, None] * X), np.eye(k), atol=1e-12)
+    T = X @ np.array([0.7, -1.3, 0.4])
+    p = mlp.init_params(2)
+    p.w3 = rng.standard_normal(64) * 0.3   # a non-trivial learned factor
+    feat = rng.standard_normal((N, 4))
+    U = rng.standard_normal(N)
+    L, _ = mlp.group_loss(p, feat, U, T, w, X, np.zeros(N, dtype=int), 1, with_grad=False)
+    assert L == pytest.approx(1.0, abs=1e-12)
+
+
+def test_adam_three_steps_match_torch():
+    """Three Adam steps with different gradients each step against torch.optim.Adam
+    (an independent implementation of Kingma & Ba's update with bias corrections
+    1 - beta^t): the bias correction's power of t shows from the second step on,
+    which a first step alone cannot reveal."""
+    import torch
+    p = mlp.init_params(4)
+    rng = np.random.default_rng(5)
+    grads = []
+    for t in range(3):
+        g = {k: rng.standard_normal(np.shape(getattr(p, k))) * (1.0 + t) for k in mlp.Params.NAMES}
+        g["b3"] = float(rng.standard_normal())
+        grads.append(g)
+    lr = 3e-3
+    st = mlp.adam_init(p)
+    q = p
+    tens = {k: torch.tensor(np.asarray(getattr(p, k), dtype=np.float64), requires_grad=True)
+            for k in mlp.Params.NAMES}
+    opt = torch.optim.Adam(list(tens.values()), lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    for g in grads:
+        q = mlp.adam_step(q, g, st, lr=lr)
+        opt.zero_grad()
+        for k, tt in tens.items():
+            tt.grad = torch.tensor(np.asarray(g[k], dtype=np.float64))
+        opt.step()
+        for k, tt in tens.items():
+            np.testing.assert_allclose(np.asarray(getattr(q, k), dtype=np.float64), tt.detach().numpy(),
+                                       rtol=1e-13, atol=1e-15)
+    assert st.t == 3
