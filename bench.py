@@ -44,7 +44,7 @@ def kernel_source_hash():
     """SHA-256 of the sparse-product kernel source."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("spmm.hip",):
+    for f in ("spmm.hip", "spmm_tiled.hip"):
         with open(os.path.join(ROOT, "paper_2109_00485_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -172,8 +172,8 @@ void free_ctx(lobpcg_ctx *c) {
     if (!c) return;
     void *ptrs[] = {c->rp, c->ci, c->val, c->diag, c->cp, c->cri, c->cval, c->feat_rownorm, c->feat_tilemean, c->X, c->W, c->P,
                     c->HX, c->HW, c->HP, c->gram_partial, c->gram_out, c->gram_out2, c->rr_C, c->rr_theta,
-                    c->orth_rinv, c->norm_partial, c->report_dev, c->dflags, c->tiled.rix, c->tiled.cix,
-                    c->tiled.rlist_off, c->tiled.rlist, c->tiled.clist_off, c->tiled.clist, c->harvest_counter,
+                    c->orth_rinv, c->norm_partial, c->report_dev, c->dflags, c->tiled.data, c->tiled.woff,
+                    c->tiled.wdesc, c->tiled.wbeg, c->tiled.list, c->harvest_counter,
                     c->heavy_rows};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

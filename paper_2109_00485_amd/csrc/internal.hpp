@@ -46,19 +46,20 @@ struct Report {
     double pad[6];
 };
 
-// Compressed-index (tiled) form of the two traversals: 16-bit
-// (slot << 6 | local index) per entry, with per-tile-row lists of the 64-wide
-// tile columns (row view) and tile rows (column view) the slots refer to.
-// Every row segment is padded to a multiple of 8 entries; the context's
-// rp/cp/val/cval then describe the padded views.
+// Tiled format: per 64-row tile-row a stream of windows over its row view and
+// then its column view; a window covers up to `ws` consecutive 64-wide blocks
+// ("slots") of X and holds, contiguously in `data`, a table of per-row chunk
+// offsets, 16-bit codes (slot within the window << 6 | local index) and the
+// values, each row padded to whole 4-entry chunks (see spmm_tiled.hip).
 struct TiledFormat {
-    int64_t ntilerows = 0, nslots_row = 0, nslots_col = 0, nent_row = 0, nent_col = 0;
-    uint16_t *rix = nullptr;       // row view, aligned with the CSR entries
-    uint16_t *cix = nullptr;       // column view, aligned with the CSC entries
-    int32_t *rlist_off = nullptr;  // ntilerows+1
-    int32_t *rlist = nullptr;      // tile-column index per row-view slot
-    int32_t *clist_off = nullptr;  // ntilerows+1
-    int32_t *clist = nullptr;      // tile-row index per column-view slot
+    int64_t ntilerows = 0, nwin = 0, nbytes = 0, nslots = 0, nent = 0;
+    int ws = 0;                    // slots per window, at most
+    int emax = 0;                  // chunk-padded entries of the largest window
+    char *data = nullptr;          // window blocks
+    int64_t *woff = nullptr;       // nwin + 1 byte offsets into data
+    int2 *wdesc = nullptr;         // per window: first slot in `list`, slot count
+    int32_t *wbeg = nullptr;       // ntilerows + 1: first window of each tile-row
+    int32_t *list = nullptr;       // per slot: the 64-wide block of X it stages
 };
 
 // Learned preconditioner: FP32 master parameters (the host blob layout) and
@@ -142,6 +143,12 @@ static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b)
 
 // launchers implemented across the .hip files --------------------------------
 int launch_spmm(lobpcg_ctx *ctx, const void *X, void *Y, int k, hipStream_t s);
+// tiled format from host copies of both views of the strict upper triangle
+// (CSR rp/ci/val and CSC cp/ri/cv); leaves the CSR format in place when the
+// automatic choice finds the tiles too sparse
+int build_tiled_format(lobpcg_ctx *ctx, const int64_t *rp, const int32_t *ci, const void *val, const int64_t *cp,
+                       const int32_t *ri, const void *cv, hipStream_t s);
+int spmm_tiled(lobpcg_ctx *ctx, const void *X, void *Y, int k, hipStream_t s);
 int launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 
 // Gram: G = A^T B with A = [a_0 .. a_{na-1}] (each n x wa), B = [b_0 ..] (each n x wb).

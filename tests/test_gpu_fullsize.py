@@ -137,3 +137,42 @@ def test_precision_variant_bf16x3_certified():
             assert np.all(err <= 1e-6 * np.maximum(np.abs(lam), tau)), err
         ctx.close()
     torch.cuda.synchronize()
+
+
+def golden_eigs(name, seed):
+    """Lowest five eigenvalues stored by tests/golden/make_eig_goldens.py (FP64 oracle only)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"eig_{name}_seed{seed}.txt")
+    vals = [float(s) for s in open(path) if s.strip() and not s.startswith("#")]
+    assert len(vals) == 5
+    return np.array(vals)
+
+
+@pytest.mark.parametrize("name,seed,offset", [("tiled_2m", 0, 0.0), ("tiled_2m", 0, 4.0),
+                                              ("random_sym_2m", 1000, 0.0)])
+def test_fullsize_eigenvalues_match_oracle_fixture(name, seed, offset):
+    """The lowest five Ritz values of the FP32 solve at full size (the bench's
+    launch configuration: k = 8, nev = 5, tol 1e-6) against the FP64 oracle's
+    eigenvalues of the same matrix (two independent oracle solves, stored with
+    their residuals): |theta_j - lambda_j| <= 1e-6 max(|lambda_j|, tau)."""
+    torch = torch_cuda()
+    if name == "tiled_2m":
+        A, _ = tiled()
+    else:
+        A = W.make_matrix(name, seed=seed)
+    lam = golden_eigs(name, seed)
+    ctx = upload(A, True)
+    if offset:
+        ctx.set_precond_offset(offset)
+    X = to_dev(W.initial_block(A.n, 8, seed=1, dtype=np.float32), np.float32)
+    r = ctx.solve(X, 5, tol=1e-6, maxiter=5000)
+    assert r.status == 0, r
+    th = r.evals[:5]
+    tau = 1e-3 * r.gamma
+    err = np.abs(th - lam)
+    print(f"{name} offset {offset}: {r.iters} iterations; |theta - lambda| {err}; relative to |lambda| "
+          f"{err / np.abs(lam)}; relative to max(|lambda|, tau) {err / np.maximum(np.abs(lam), tau)} "
+          f"(tau {tau:.4g}; {int(np.sum(np.abs(lam) < tau))} of 5 below tau)")
+    assert np.all(err <= 1e-6 * np.maximum(np.abs(lam), tau)), err
+    ctx.close()
+    torch.cuda.synchronize()

@@ -72,25 +72,25 @@ def test_spmm_integer_bitwise(k, fmt, hubs):
 
 
 def test_format_choice():
-    """AUTO picks 16-bit tile indices when every 64-row tile-row touches at most
-    1023 tile columns, 32-bit indices otherwise; forcing TILED then fails cleanly."""
+    """AUTO picks the tiled format when the stored entries fill the 64 x 64
+    tiles they touch densely enough (at least 8 entries per touched tile on
+    average), 32-bit CSR indices otherwise; a forced tiled format works on the
+    sparse-tiled matrix too.  Both give the oracle's rows."""
     import paper_2109_00485_amd as L
     torch = torch_cuda()
     A = synth.tiled(64 * 200, tile_draws=20, p=0.05, seed=3)
     assert upload(A, True).query()["format"] == L.FORMAT_TILED
-    B = synth.random_sym(200_000, 50, seed=3, f32=True)   # ~6400 tile columns per tile-row
-    assert upload(B, True).query()["format"] == L.FORMAT_CSR
-    with pytest.raises(L.LobpcgError) as e:
-        upload(B, True, fmt=L.FORMAT_TILED)
-    assert e.value.status == L.EUNSUPPORTED
-    # the CSR result on the wide matrix still matches the oracle at sampled rows
-    ctx = upload(B, True)
-    X = synth.gaussian_block(B.n, 8, seed=2).astype(np.float32)
-    Y = ctx.spmm_sym(to_dev(X, np.float32)).cpu().numpy()
+    B = synth.random_sym(200_000, 50, seed=3, f32=True)   # ~1 entry per touched tile
     H = oracle.SymMatrix.from_csr(B)
+    X = synth.gaussian_block(B.n, 8, seed=2).astype(np.float32)
     rows = np.random.default_rng(0).choice(B.n, 2000, replace=False)
     Yr, Ya = H.rows(X.astype(np.float64), rows)
-    assert row_error(Y[rows], Yr, Ya) <= 1e-5
+    for fmt, want in ((None, L.FORMAT_CSR), (L.FORMAT_TILED, L.FORMAT_TILED)):
+        ctx = upload(B, True, fmt=fmt)
+        assert ctx.query()["format"] == want
+        Y = ctx.spmm_sym(to_dev(X, np.float32)).cpu().numpy()
+        assert row_error(Y[rows], Yr, Ya) <= 1e-5
+        ctx.close()
 
 
 def test_spmm_repeatable_and_no_alias():
