@@ -51,10 +51,11 @@ def kernel_source_hash():
 
 
 def counter_traffic(workload, k):
-    """HBM-side bytes per sparse product from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, each counter scaled by what it read for a
-    plain copy of known size.  None when there is no summary for this
-    workload or the kernel sources changed since the counters were taken."""
+    """Bytes per sparse product beyond the L2 from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, each counter scaled by what it read for the
+    library's plain read / write probe kernels of known size in the same run.
+    None when there is no summary for this workload or the kernel sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"spmm_{workload}_k{k}_counters.txt")
     if not os.path.exists(path):
         return None, None
@@ -67,9 +68,9 @@ def counter_traffic(workload, k):
     try:
         if kv.get("source_sha256") != kernel_source_hash():
             return None, "kernel sources changed since the counters were taken"
-        cb = float(kv["copy_bytes_each_way"])
-        f_fetch = cb / (float(kv["copy_fetch_kib"]) * 1024)
-        f_write = cb / (float(kv["copy_write_kib"]) * 1024)
+        pb = float(kv["probe_bytes"])
+        f_fetch = pb / (float(kv["read_probe_fetch_kib"]) * 1024)
+        f_write = pb / (float(kv["write_probe_write_kib"]) * 1024)
         t = float(kv["kernel_fetch_kib"]) * 1024 * f_fetch + float(kv["kernel_write_kib"]) * 1024 * f_write
         return t, dict(fetch_scale=round(f_fetch, 4), write_scale=round(f_write, 4), source=os.path.relpath(path, ROOT))
     except (KeyError, ValueError) as e:
@@ -221,41 +222,47 @@ def main():
     torch.cuda.synchronize()
     spmm_ms = s0.elapsed_time(s1) / args.spmm_reps
     log(f"standalone spmm: {spmm_ms:.3f} ms, {nbytes / spmm_ms / 1e6:.1f} GB/s")
-    copy_gbs = None
+    copy_gbs = read_gbs = None
     if not args.spmm_only:
-        # achievable HBM bandwidth on this GPU: a plain 2 GiB device copy (reads
-        # 2 GiB, writes 2 GiB; 8x the 256 MB last-level cache), HIP events
+        # achievable HBM bandwidth on this GPU: the library's plain streaming
+        # kernels on 2 GiB buffers (8x the 256 MB last-level cache), HIP events
         a = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         a.fill_(1.0)
-        for _ in range(2):
-            b.copy_(a)
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record()
-        for _ in range(5):
-            b.copy_(a)
-        c1.record()
-        torch.cuda.synchronize()
-        copy_gbs = 2 * a.numel() * 4 / (c0.elapsed_time(c1) / 5) / 1e6
+        nb = a.numel() * 4
+        rates = {}
+        for op, moved in ((L.PROBE_COPY, 2 * nb), (L.PROBE_READ, nb)):
+            for _ in range(2):
+                L.stream_probe(op, a, b, nb)
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record()
+            for _ in range(5):
+                L.stream_probe(op, a, b, nb)
+            c1.record()
+            torch.cuda.synchronize()
+            rates[op] = moved / (c0.elapsed_time(c1) / 5) / 1e6
+        copy_gbs, read_gbs = rates[L.PROBE_COPY], rates[L.PROBE_READ]
         del a, b
         torch.cuda.empty_cache()
-        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+        log(f"stream probes: copy {copy_gbs:.0f} GB/s (read + write), read {read_gbs:.0f} GB/s")
     if args.spmm_only:
         out = {"mode": "spmm-only", "workload": args.workload, "n": A.n, "nnz_stored": A.nnz, "format": q["format"],
                "k": args.k, "reps": args.spmm_reps,
                "spmm_ms": round(spmm_ms, 4), "gbs": round(nbytes / spmm_ms / 1e6, 2), "bytes": int(nbytes)}
         if args.copy_calibration:
-            # a plain copy kernel of known size: reads 2 GiB, writes 2 GiB (8x the
-            # 256 MB last-level cache, so neither side stays cache-resident)
+            # the library's plain read, write and copy kernels on 2 GiB (8x the 256 MB
+            # last-level cache, so nothing stays cache-resident): transfers of known
+            # size that scale the traffic counters read for the sparse product
             a = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
             b = torch.empty_like(a)
             a.fill_(1.0)
             b.fill_(0.0)
             torch.cuda.synchronize()
-            for _ in range(3):
-                b.copy_(a)
+            for op in (L.PROBE_READ, L.PROBE_WRITE, L.PROBE_COPY):
+                for _ in range(3):
+                    L.stream_probe(op, a, b, a.numel() * 4)
             torch.cuda.synchronize()
-            out["copy_bytes_each_way"] = a.numel() * 4
+            out["probe_bytes"] = a.numel() * 4
         print(json.dumps(out), flush=True)
         return
 
@@ -371,7 +378,9 @@ def main():
                      # the same kernel against the copy bandwidth measured above, and the
                      # rate of the bytes it actually moves (counter traffic / launch time)
                      "copy_GBps": None if copy_gbs is None else round(copy_gbs, 1),
+                     "read_GBps": None if read_gbs is None else round(read_gbs, 1),
                      "frac_of_copy": None if copy_gbs is None else round(gbs / copy_gbs, 4),
+                     "frac_of_read": None if read_gbs is None else round(gbs / read_gbs, 4),
                      "traffic_GBps": None if traffic is None else round(traffic / (spmm_in_solve_ms * 1e6), 1)},
     }
     if not args.no_learned:

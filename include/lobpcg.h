@@ -313,6 +313,19 @@ int lobpcg_query(const lobpcg_ctx *ctx, int64_t *n, int64_t *nnz, int *format, i
 /* Device copy of the diagonal d (n values, context dtype) into `d`. */
 int lobpcg_get_diag(lobpcg_ctx *ctx, void *d, void *stream);
 
+/* Streaming probes of the memory system (not part of the method): a plain
+ * kernel that reads `bytes` from a (op LOBPCG_PROBE_READ; b receives at most
+ * one float and must hold 4 bytes), writes `bytes` to b (LOBPCG_PROBE_WRITE;
+ * a unused), or copies a to b (LOBPCG_PROBE_COPY; a and b must not overlap).
+ * bytes > 0 and a multiple of 16; pointers device, 16-byte aligned,
+ * caller-owned.  Asynchronous on `stream`.  Used for the achievable-bandwidth
+ * reference of the sparse product and to scale hardware traffic counters by
+ * a transfer of known size; LOBPCG_EINVAL on a bad argument. */
+#define LOBPCG_PROBE_READ  0
+#define LOBPCG_PROBE_WRITE 1
+#define LOBPCG_PROBE_COPY  2
+int lobpcg_stream_probe(int op, const void *a, void *b, int64_t bytes, void *stream);
+
 const char *lobpcg_strerror(int status);
 const char *lobpcg_last_error(const lobpcg_ctx *ctx);
 

@@ -132,8 +132,23 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_mlp_train_step.argtypes = [P, ctypes.POINTER(MlpBatch), ctypes.c_float, ctypes.POINTER(dbl), P]
     lib.lobpcg_harvest_block.restype = cint
     lib.lobpcg_harvest_block.argtypes = [P, P, P, P, cint, ctypes.POINTER(Harvest), P]
+    lib.lobpcg_stream_probe.restype = cint
+    lib.lobpcg_stream_probe.argtypes = [cint, P, P, i64, P]
     _lib = lib
     return lib
+
+
+PROBE_READ, PROBE_WRITE, PROBE_COPY = 0, 1, 2
+
+
+def stream_probe(op, a, b, nbytes, stream=None):
+    """lobpcg_stream_probe: plain read / write / copy of ``nbytes`` on the device
+    (a, b: CUDA tensors, 16-byte aligned)."""
+    rc = load().lobpcg_stream_probe(int(op), ctypes.c_void_p(a.data_ptr()) if a is not None else None,
+                                    ctypes.c_void_p(b.data_ptr()) if b is not None else None, int(nbytes),
+                                    _stream_ptr(stream))
+    if rc != OK:
+        raise LobpcgError(rc, "stream_probe: " + load().lobpcg_strerror(rc).decode())
 
 
 def default_opts() -> Opts:

@@ -39,19 +39,24 @@ constexpr int CH = 4;            // entries per chunk
 #ifndef LOBPCG_TILE_TG
 #define LOBPCG_TILE_TG 4         // lanes per output row
 #endif
-#ifndef LOBPCG_TILE_WAVES
-#define LOBPCG_TILE_WAVES 0      // waves-per-SIMD hint for the register allocator (0: none)
+#ifndef LOBPCG_TILE_WS
+#define LOBPCG_TILE_WS 8         // 64-wide blocks of X per window (FP32; half as many in FP64)
+#endif
+#ifndef LOBPCG_TILE_ECAP
+#define LOBPCG_TILE_ECAP 320     // chunk-padded entries per window, per block it may hold
 #endif
 constexpr int TG = LOBPCG_TILE_TG;
 constexpr int THREADS = 64 * TG;
 constexpr int NWAVE = THREADS / LOBPCG_WAVE;
 constexpr int MAXJ = 8;          // X wave-loads per wave and window (ws * row bytes / 16 <= MAXJ * NWAVE)
 
-#if LOBPCG_TILE_WAVES > 0
-#define TILE_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(LOBPCG_TILE_WAVES)))
-#else
-#define TILE_WAVES_ATTR
-#endif
+// Register budget: the FP32 k = 8 instantiation is held to five waves per SIMD
+// (its LDS allows four to five workgroups per CU; measured 2% faster than the
+// allocator's own choice of four waves); the others keep the allocator's.
+template <typename T, int KP>
+struct TileWaves {
+    static constexpr int value = (sizeof(T) == 4 && KP == 8) ? 5 : 1;
+};
 
 __host__ __device__ inline int round16(int64_t b) { return (int)((b + 15) & ~(int64_t)15); }
 
@@ -64,7 +69,7 @@ __host__ __device__ inline int m_bytes(int emax, int esz) { return TAB_BYTES + r
 // registers with the columns beyond k set to zero.  LDS rows are always KP
 // wide, so the compute loop never branches on k.
 template <typename T, int KP, bool FULL>
-__global__ __launch_bounds__(THREADS) TILE_WAVES_ATTR void spmm_window_kernel(
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(TileWaves<T, KP>::value))) void spmm_window_kernel(
     int64_t n, int k, int ws, int emax, const char *__restrict__ data, const int64_t *__restrict__ woff,
     const int2 *__restrict__ wdesc, const int32_t *__restrict__ wbeg, const int32_t *__restrict__ list,
     const T *__restrict__ diag, const T *__restrict__ X, T *__restrict__ Y) {
@@ -293,8 +298,8 @@ int build_windows(lobpcg_ctx *ctx, const int64_t *rp, const int32_t *ci, const T
     const int esz = (int)sizeof(T);
     // window size: 8 blocks of X (16 KB at k = 8 in FP32) for FP32, 4 for FP64,
     // and about 320 chunk-padded entries per slot
-    const int ws = esz == 4 ? 8 : 4;
-    const int64_t ecap = (int64_t)ws * 320;
+    const int ws = esz == 4 ? LOBPCG_TILE_WS : std::max(1, LOBPCG_TILE_WS / 2);
+    const int64_t ecap = (int64_t)ws * LOBPCG_TILE_ECAP;
     unsigned hw = std::thread::hardware_concurrency();
     const int nth = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
     auto parallel = [&](auto &&fn) {
