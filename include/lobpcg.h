@@ -170,6 +170,23 @@ int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B, int kb, d
                 int prec, void *stream);
 
 /*
+ * lobpcg_gram_noalloc -- the product of lobpcg_gram without a context and
+ * without allocating anything, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, allocation-free
+ * harnesses): G = A^T B for two tall-skinny blocks.
+ *   A      device, n x ka row-major;  B device, n x kb row-major (may alias A)
+ *   n      rows, >= 1;  dtype LOBPCG_F32 or LOBPCG_F64 (of A and B)
+ *   G      device, double[ka*kb], row-major ka x kb, overwritten
+ *   prec   a LOBPCG_GRAM_* value; AUTO means FP64 (BF16X3 and F32 need F32 data)
+ * The partial sums live in one library-owned device array per GPU (4.8 MB,
+ * held until the process ends), so 1 <= ka, kb <= 48 (LOBPCG_EUNSUPPORTED
+ * beyond) and calls that overlap on one GPU race: serialise them (one stream,
+ * or events).  Asynchronous on `stream`; LOBPCG_EINVAL on a bad argument.
+ */
+int lobpcg_gram_noalloc(const void *A, int ka, const void *B, int kb, int64_t n, int dtype, double *G, int prec,
+                        void *stream);
+
+/*
  * lobpcg_solve -- lowest nev eigenpairs by Algorithm 1.
  *   k        block size, nev <= k <= kmax, 3k <= n
  *   X        device, n x k row-major: the starting block X0 on entry, the Ritz

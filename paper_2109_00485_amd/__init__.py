@@ -132,6 +132,8 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_mlp_train_step.argtypes = [P, ctypes.POINTER(MlpBatch), ctypes.c_float, ctypes.POINTER(dbl), P]
     lib.lobpcg_harvest_block.restype = cint
     lib.lobpcg_harvest_block.argtypes = [P, P, P, P, cint, ctypes.POINTER(Harvest), P]
+    lib.lobpcg_gram_noalloc.restype = cint
+    lib.lobpcg_gram_noalloc.argtypes = [P, cint, P, cint, i64, cint, P, cint, P]
     lib.lobpcg_stream_probe.restype = cint
     lib.lobpcg_stream_probe.argtypes = [cint, P, P, i64, P]
     _lib = lib

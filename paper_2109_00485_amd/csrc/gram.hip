@@ -16,6 +16,8 @@
 // A[i = l % 16][kk] and B[kk][j = l % 16] for the kk owned by lane group l / 16;
 // the four outputs of lane l are D[4 * (l / 16) + r][l % 16], r = 0..3, for the
 // FP32-accumulating instructions and D[l / 16 + 4 * r][l % 16] for the FP64 one.
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace {
@@ -292,4 +294,80 @@ extern "C" int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_err(ctx, LOBPCG_EHIP, "gram launch: %s", hipGetErrorString(e));
     return LOBPCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Context-free Gram product that allocates nothing: its workgroup partials and
+// reduction rows live in a file-scope device array, one copy per GPU, held
+// until the process ends.  At most NOALLOC_MAX_WG workgroups (each walks as
+// many 16-row slabs as n needs) and ka, kb <= 48, so the array is
+// (NOALLOC_MAX_WG + NOALLOC_MAX_WG / RB + 1) * 48 * 48 doubles = 4.8 MB.
+namespace {
+constexpr int NOALLOC_MAX_WG = 256;
+constexpr int NOALLOC_MAX_K = 48;
+constexpr size_t NOALLOC_SLOT = (size_t)NOALLOC_MAX_K * NOALLOC_MAX_K;
+constexpr size_t NOALLOC_DOUBLES = (size_t)(NOALLOC_MAX_WG + NOALLOC_MAX_WG / RB + 1) * NOALLOC_SLOT;
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex noalloc_mu;
+double *noalloc_ptr[NOALLOC_MAX_DEV] = {};
+
+// the device address of this GPU's copy of `scratch` (looked up once per device,
+// with that device current): host code passes this pointer, never the symbol
+int scratch_for_current_device(double **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LOBPCG_EHIP;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) return LOBPCG_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LOBPCG_EHIP;
+        noalloc_ptr[dev] = (double *)p;
+    }
+    *out = noalloc_ptr[dev];
+    return LOBPCG_OK;
+}
+}  // namespace
+
+extern "C" int lobpcg_gram_noalloc(const void *A, int ka, const void *B, int kb, int64_t n, int dtype, double *G,
+                                   int prec, void *stream) {
+    if (!A || !B || !G || n < 1) return LOBPCG_EINVAL;
+    if (ka < 1 || kb < 1) return LOBPCG_EINVAL;
+    if (ka > NOALLOC_MAX_K || kb > NOALLOC_MAX_K) return LOBPCG_EUNSUPPORTED;   // beyond the static scratch
+    if (dtype != LOBPCG_F32 && dtype != LOBPCG_F64) return LOBPCG_EINVAL;
+    if (prec < LOBPCG_GRAM_AUTO || prec > LOBPCG_GRAM_BF16X3) return LOBPCG_EINVAL;
+    if (prec == LOBPCG_GRAM_AUTO) prec = LOBPCG_GRAM_F64;
+    if (dtype == LOBPCG_F64 && prec != LOBPCG_GRAM_F64) return LOBPCG_EINVAL;
+    double *scr = nullptr;
+    int rc = scratch_for_current_device(&scr);
+    if (rc != LOBPCG_OK) return rc;
+    GramDev g;
+    for (int i = 0; i < 3; ++i) g.a[i] = nullptr;
+    for (int i = 0; i < 6; ++i) g.b[i] = nullptr;
+    g.a[0] = A;
+    g.b[0] = B;
+    g.na = g.nb = 1;
+    g.wa = ka;
+    g.wb = kb;
+    g.n = n;
+    const int MT = (ka + 15) / 16, NT = (kb + 15) / 16;
+    const int64_t nslab = (n + 15) / 16;
+    const int grid = (int)std::min<int64_t>(NOALLOC_MAX_WG, std::max<int64_t>(1, (nslab + 4 * GRAM_WAVES - 1) / (4 * GRAM_WAVES)));
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == LOBPCG_F64)
+        rc = dispatch_tiles<double, M_F64>(MT, NT, grid, g, scr, s);
+    else if (prec == LOBPCG_GRAM_F64)
+        rc = dispatch_tiles<float, M_F64>(MT, NT, grid, g, scr, s);
+    else if (prec == LOBPCG_GRAM_F32)
+        rc = dispatch_tiles<float, M_F32>(MT, NT, grid, g, scr, s);
+    else
+        rc = dispatch_tiles<float, M_BF16X3>(MT, NT, grid, g, scr, s);
+    if (rc != LOBPCG_OK) return rc;
+    const int count = ka * kb;
+    const int nstage = ceil_div(grid, RB);
+    double *stage = scr + (size_t)NOALLOC_MAX_WG * NOALLOC_SLOT;
+    gram_reduce1_kernel<<<dim3(ceil_div(count, 64), nstage), 256, 0, s>>>(scr, grid, count, stage);
+    gram_reduce2_kernel<<<ceil_div(count, 256), 256, 0, s>>>(stage, nstage, count, G);
+    return hipGetLastError() == hipSuccess ? LOBPCG_OK : LOBPCG_EHIP;
 }
