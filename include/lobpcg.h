@@ -91,6 +91,9 @@ typedef struct {
     double t_spmm, t_precond_update, t_gram, t_rr, t_orth, t_total;
     /* optional training-sample harvest (struct lobpcg_harvest below), NULL = off */
     struct lobpcg_harvest_s *harvest;
+    int cholqr_shifted;       /* iterations whose Cholesky QR needed the diagonal shift */
+    long long mlp_fallbacks;  /* entries where the learned factor was not finite and
+                                 the diagonal step was used alone                     */
 } lobpcg_info;
 
 /* Fill *o with the defaults: F32, GRAM_AUTO, FORMAT_AUTO, tile 64, kmax 16,
@@ -145,6 +148,29 @@ int lobpcg_spmm_sym(lobpcg_ctx *ctx, const void *X, void *Y, int k, void *stream
  */
 int lobpcg_precond_apply(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k,
                          int kind, void *stream);
+
+/*
+ * lobpcg_set_test_faults -- force the failure branches of the solver at one
+ * iteration of the following lobpcg_solve calls, for tests of the error paths
+ * (the kernels then take the branch as if the factorisation had failed; no
+ * kernel is made to fault).  iteration 0 is the first Rayleigh-Ritz step (on
+ * X0), 1 the first LOBPCG iteration.  mask (0 turns it off) is an OR of
+ *   LOBPCG_FAULT_CHOLQR_SHIFT   the unshifted Cholesky of W^T W fails: the
+ *                               shifted factorisation (Section 3.5) is used
+ *   LOBPCG_FAULT_CHOLQR_ONCE    both fail on the first attempt: W is projected
+ *                               again and the retry proceeds
+ *   LOBPCG_FAULT_CHOLQR_ALWAYS  both fail on every attempt: LOBPCG_ENOTSPD
+ *   LOBPCG_FAULT_RR_DROP_P      the Rayleigh-Ritz Cholesky of O fails with P:
+ *                               P is dropped for that iteration
+ *   LOBPCG_FAULT_RR             it fails with and without P: LOBPCG_ENOTSPD
+ * Returns LOBPCG_EINVAL for unknown bits or a negative iteration.  Host-only.
+ */
+#define LOBPCG_FAULT_CHOLQR_SHIFT  1
+#define LOBPCG_FAULT_CHOLQR_ONCE   2
+#define LOBPCG_FAULT_CHOLQR_ALWAYS 4
+#define LOBPCG_FAULT_RR_DROP_P     8
+#define LOBPCG_FAULT_RR            16
+int lobpcg_set_test_faults(lobpcg_ctx *ctx, int mask, int iteration);
 
 /*
  * lobpcg_set_precond_offset -- place the diagonal preconditioner's shift c

@@ -4,10 +4,14 @@ Cholesky QR (paper Section 3.5):  B = W^T W,  B = R^T R,  W <- W R^{-1}.
 Gram blocks (eq. Glower): only the lower blocks of G = S^T H S and
 O = S^T S are formed; each upper block is the transpose of its lower
 counterpart, and each diagonal block is averaged with its own transpose.
-Rayleigh-Ritz (eq. rreig): the pencil (G, O) is reduced with the Cholesky
-factor of O and solved by a symmetric eigensolver; the k leftmost Ritz pairs
-are kept, in ascending order (the paper calls LAPACK dsygv, which does the same
-reduction).
+Rayleigh-Ritz (eq. rreig): the pencil (G, O), scaled to a unit diagonal of O,
+is reduced with the Cholesky factor of O and solved by a symmetric
+eigensolver; the k leftmost Ritz pairs are kept, in ascending order (the paper
+calls LAPACK dsygv, which does the same reduction).  O counts as not positive
+definite (the caller then drops P) when that Cholesky factor has a squared
+pivot at or below RR_PIVOT_TOL: a basis that nearly lost a direction passes a
+plain Cholesky but the reduced pencil then yields Ritz values outside the
+spectrum.
 """
 from __future__ import annotations
 
@@ -17,6 +21,10 @@ import scipy.linalg as sla
 
 class NotSPD(np.linalg.LinAlgError):
     pass
+
+
+# smallest squared pivot accepted in the Cholesky of the unit-diagonal-scaled O
+RR_PIVOT_TOL = 1e-7
 
 
 def gram(A: np.ndarray, B: np.ndarray) -> np.ndarray:
@@ -89,13 +97,27 @@ def assemble_pencil(S: list[np.ndarray], HS: list[np.ndarray]) -> tuple[np.ndarr
 def rayleigh_ritz(G: np.ndarray, O: np.ndarray, k: int) -> tuple[np.ndarray, np.ndarray]:
     """Solve G C = O C D (eq. rreig); return the k leftmost (theta, C), ascending.
 
-    O = L L^T;  A = L^{-1} G L^{-T};  A V = V D;  C = L^{-T} V.
-    Raises NotSPD if O is not positive definite.
+    The pencil is first scaled to a unit diagonal of O (D = diag(O)^-1/2,
+    G' = D G D, O' = D O D: the same eigenvalues, eigenvectors C = D C'), as
+    if every basis column had unit norm; a Cholesky QR of an ill-conditioned W
+    leaves columns whose norms are far from 1, and the unscaled reduction then
+    loses the small directions of O.  Then O' = L L^T, A = L^{-1} G' L^{-T},
+    A V = V D, C' = L^{-T} V.  Raises NotSPD if O is not positive definite or
+    nearly singular: a squared pivot of L at or below RR_PIVOT_TOL.
     """
-    L = cholesky_upper(O).T
-    Linv_G = sla.solve_triangular(L, G, lower=True)
+    dg = np.diag(O)
+    if np.any(dg <= 0):
+        raise NotSPD("zero column in the Rayleigh-Ritz basis")
+    s = 1.0 / np.sqrt(dg)
+    Gs = G * np.outer(s, s)
+    Os = O * np.outer(s, s)
+    R = cholesky_upper(Os)
+    if np.min(np.diag(R)) ** 2 <= RR_PIVOT_TOL:
+        raise NotSPD("nearly singular Rayleigh-Ritz basis")
+    L = R.T
+    Linv_G = sla.solve_triangular(L, Gs, lower=True)
     A = sla.solve_triangular(L, Linv_G.T, lower=True).T
     A = 0.5 * (A + A.T)
     d, V = np.linalg.eigh(A)
     C = sla.solve_triangular(L.T, V[:, :k], lower=False)
-    return d[:k].copy(), C
+    return d[:k].copy(), C * s[:, None]

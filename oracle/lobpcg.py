@@ -59,6 +59,7 @@ class Result:
     resid_hist: list = field(default_factory=list)
     p_dropped: int = 0
     cholqr_shifts: int = 0
+    cholqr_retries: int = 0          # Cholesky QRs retried after projecting W again
 
 
 def rel_residuals(R: np.ndarray, X: np.ndarray, theta: np.ndarray, tau: float) -> np.ndarray:
@@ -145,16 +146,27 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
             callback(it, X, R, theta, W)
         # orthogonalise against X, then Cholesky QR (Section 3.5); a shifted
         # Cholesky QR is the fallback when W^T W is numerically singular
+        # (if the shifted one fails too, W is projected once more and both are
+        # tried again before giving up)
         W = W - X @ gram(X, W)
-        try:
-            W, _ = cholqr(W)
-        except NotSPD:
+        orthonormal = False
+        for attempt in range(2):
             try:
-                W, _ = cholqr(W, shift=1e-12)
-                res.cholqr_shifts += 1
+                W, _ = cholqr(W)
+                orthonormal = True
             except NotSPD:
-                res.status = ENOTSPD
+                try:
+                    W, _ = cholqr(W, shift=1e-12)
+                    res.cholqr_shifts += 1
+                    orthonormal = True
+                except NotSPD:
+                    res.cholqr_retries += attempt == 0
+                    W = W - X @ gram(X, W)
+            if orthonormal:
                 break
+        if not orthonormal:
+            res.status = ENOTSPD
+            break
         HW = H @ W
         n_spmm += 1
         # Rayleigh-Ritz on S = [X, W, P] (eq. rreig)

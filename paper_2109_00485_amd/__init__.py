@@ -45,7 +45,7 @@ class Info(ctypes.Structure):
                 ("timing", ctypes.c_int),
                 ("t_spmm", ctypes.c_double), ("t_precond_update", ctypes.c_double), ("t_gram", ctypes.c_double),
                 ("t_rr", ctypes.c_double), ("t_orth", ctypes.c_double), ("t_total", ctypes.c_double),
-                ("harvest", ctypes.c_void_p)]
+                ("harvest", ctypes.c_void_p), ("cholqr_shifted", ctypes.c_int), ("mlp_fallbacks", ctypes.c_longlong)]
 
 
 MLP_NIN, MLP_HID, MLP_NPARAM, MLP_NBLOB = 4, 64, 4545, 4553
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_mlp_last_error.argtypes = [P]
     lib.lobpcg_set_mlp.restype = cint
     lib.lobpcg_set_mlp.argtypes = [P, P]
+    lib.lobpcg_set_test_faults.restype = cint
+    lib.lobpcg_set_test_faults.argtypes = [P, cint, cint]
     lib.lobpcg_set_precond_offset.restype = cint
     lib.lobpcg_set_precond_offset.argtypes = [P, dbl]
     lib.lobpcg_get_features.restype = cint
@@ -141,6 +143,7 @@ def load(path: str = LIB_PATH):
 
 
 PROBE_READ, PROBE_WRITE, PROBE_COPY = 0, 1, 2
+FAULT_CHOLQR_SHIFT, FAULT_CHOLQR_ONCE, FAULT_CHOLQR_ALWAYS, FAULT_RR_DROP_P, FAULT_RR = 1, 2, 4, 8, 16
 
 
 def stream_probe(op, a, b, nbytes, stream=None):
@@ -188,6 +191,8 @@ class SolveResult:
     confirmations: int
     refreshes: int
     gamma: float
+    cholqr_shifted: int = 0
+    mlp_fallbacks: int = 0
     times: dict = field(default_factory=dict)
     theta_hist: Optional[np.ndarray] = None
     rel_hist: Optional[np.ndarray] = None
@@ -291,6 +296,10 @@ class Context:
                                        _dev_ptr(G, torch.float64, "G"), prec, _stream_ptr(stream)), "gram")
         return G
 
+    def set_test_faults(self, mask: int, iteration: int = 1):
+        """lobpcg_set_test_faults: force the solver's failure branches at one iteration (tests)."""
+        self._check(load().lobpcg_set_test_faults(self._h, int(mask), int(iteration)), "set_test_faults")
+
     def set_precond_offset(self, c: float):
         """Diagonal preconditioner shift sigma_j = theta_j - c (theta_max - theta_min); 0 = theta_j."""
         self._check(load().lobpcg_set_precond_offset(self._h, float(c)), "set_precond_offset")
@@ -319,7 +328,7 @@ class Context:
         return hb
 
     def solve(self, X, nev, tol=1e-6, maxiter=5000, precond=PRECOND_DIAG, history=False, timing=False,
-              stream=None, raise_on_noconv=False, harvest=None) -> SolveResult:
+              stream=None, raise_on_noconv=False, harvest=None, raise_on_error=True) -> SolveResult:
         k = X.shape[1]
         evals = np.zeros(k)
         rel = np.zeros(k)
@@ -336,11 +345,12 @@ class Context:
         rc = load().lobpcg_solve(self._h, k, nev, _dev_ptr(X, self.torch_dtype, "X"),
                                  evals.ctypes.data_as(ctypes.c_void_p), rel.ctypes.data_as(ctypes.c_void_p),
                                  float(tol), int(maxiter), int(precond), ctypes.byref(info), _stream_ptr(stream))
-        if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
+        if (rc not in (OK, ENOCONV) and raise_on_error) or (rc == ENOCONV and raise_on_noconv):
             self._check(rc, "solve")
         res = SolveResult(evals=evals, rel=rel, status=rc, iters=info.iters, n_spmm=info.n_spmm,
                           p_dropped=info.p_dropped, cholqr_retries=info.cholqr_retries,
                           confirmations=info.confirmations, refreshes=info.refreshes, gamma=info.gamma,
+                          cholqr_shifted=info.cholqr_shifted, mlp_fallbacks=info.mlp_fallbacks,
                           times=dict(spmm=info.t_spmm, precond_update=info.t_precond_update, gram=info.t_gram,
                                      rr=info.t_rr, orth=info.t_orth, total=info.t_total))
         if history:

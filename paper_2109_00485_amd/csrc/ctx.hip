@@ -9,6 +9,9 @@
 #include "internal.hpp"
 
 int set_err(lobpcg_ctx *ctx, int code, const char *fmt, ...) {
+    // the status carries a runtime failure: clear it so the caller's next HIP call
+    // does not report it again
+    if (code == LOBPCG_EHIP || code == LOBPCG_ENOMEM) (void)hipGetLastError();
     if (ctx) {
         char buf[512];
         va_list ap;
@@ -173,7 +176,7 @@ void free_ctx(lobpcg_ctx *c) {
     void *ptrs[] = {c->rp, c->ci, c->val, c->diag, c->cp, c->cri, c->cval, c->feat_rownorm, c->feat_tilemean, c->X, c->W, c->P,
                     c->HX, c->HW, c->HP, c->gram_partial, c->gram_out, c->gram_out2, c->rr_C, c->rr_theta,
                     c->orth_rinv, c->norm_partial, c->report_dev, c->dflags, c->tiled.data, c->tiled.woff,
-                    c->tiled.wdesc, c->tiled.wbeg, c->tiled.list, c->harvest_counter,
+                    c->tiled.wdesc, c->tiled.wbeg, c->tiled.list, c->harvest_counter, c->mlp_fallback_count,
                     c->heavy_rows};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -213,6 +216,16 @@ extern "C" const char *lobpcg_strerror(int status) {
 }
 
 extern "C" const char *lobpcg_last_error(const lobpcg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" int lobpcg_set_test_faults(lobpcg_ctx *ctx, int mask, int iteration) {
+    if (!ctx) return LOBPCG_EINVAL;
+    const int all = LOBPCG_FAULT_CHOLQR_SHIFT | LOBPCG_FAULT_CHOLQR_ONCE | LOBPCG_FAULT_CHOLQR_ALWAYS |
+                    LOBPCG_FAULT_RR_DROP_P | LOBPCG_FAULT_RR;
+    if ((mask & ~all) || iteration < 0) return set_err(ctx, LOBPCG_EINVAL, "test faults: bad mask 0x%x or iteration %d", mask, iteration);
+    ctx->test_fault_mask = mask;
+    ctx->test_fault_iter = iteration;
+    return LOBPCG_OK;
+}
 
 extern "C" int lobpcg_set_precond_offset(lobpcg_ctx *ctx, double c) {
     if (!ctx) return LOBPCG_EINVAL;
@@ -256,6 +269,9 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
 
     auto fail = [&](int code) {
         free_ctx(ctx);
+        // the status carries the failure: leave no runtime error behind for the
+        // caller's next HIP call (a failed hipMalloc is otherwise reported again)
+        (void)hipGetLastError();
         return code;
     };
     int64_t nnz = 0;
@@ -308,6 +324,7 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
          hipMalloc((void **)&ctx->orth_rinv, 16 * 16 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->norm_partial, (size_t)ctx->norm_max_wg * 3 * 16 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->report_dev, sizeof(Report)) == hipSuccess &&
+         hipMalloc((void **)&ctx->mlp_fallback_count, sizeof(unsigned long long)) == hipSuccess &&
          hipHostMalloc((void **)&ctx->report_host, sizeof(Report), hipHostMallocDefault) == hipSuccess;
     for (auto &e : ctx->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     if (!ok) return fail(LOBPCG_ENOMEM);

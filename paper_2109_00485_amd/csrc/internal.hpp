@@ -36,6 +36,16 @@ enum : int {
     FLAG_CHOLQR_SHIFT = 256, // Cholesky QR needed the diagonal shift
 };
 
+// flags[2]: failure branches forced from the host for one attempt of one
+// iteration (lobpcg_set_test_faults); the kernels take the branch as if the
+// factorisation had failed, so every kernel still runs to its normal end.
+enum : int {
+    FORCE_CHOLQR_UNSHIFTED = 1,   // the unshifted Cholesky of W^T W "fails": the shifted one runs
+    FORCE_CHOLQR = 2,             // both Cholesky factorisations of W^T W "fail"
+    FORCE_RR_WITH_P = 4,          // the Rayleigh-Ritz Cholesky of O with P "fails": P is dropped
+    FORCE_RR = 8,                 // the Rayleigh-Ritz Cholesky "fails" with and without P
+};
+
 // Per-iteration report copied to the host (doubles, padded to kmax).
 struct Report {
     double theta[16];
@@ -89,6 +99,9 @@ struct lobpcg_ctx {
     // diagonal preconditioner shift sigma_j = theta_j - precond_offset * (max theta - min theta)
     double precond_offset = 0.0;
     int refresh_every = 0;  // explicit H X, H P recomputation period (0 = only on apparent convergence)
+    // failure branches forced at one iteration (tests of the error paths)
+    int test_fault_mask = 0, test_fault_iter = -1;
+    unsigned long long *mlp_fallback_count = nullptr;   // device counter of per-entry MLP fallbacks
     int device = 0;
     // strict upper triangle in CSR + diagonal
     int64_t *rp = nullptr;
@@ -171,7 +184,9 @@ int launch_rayleigh_quotients(lobpcg_ctx *ctx, int k, hipStream_t s);
 int launch_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, int kind,
                    hipStream_t s);
 int mlp_precond_ready(lobpcg_ctx *ctx);
-int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s);
+// in_solve: skip after a failed Cholesky QR / Rayleigh-Ritz and count fallbacks
+int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s,
+                       bool in_solve = false);
 // one harvest snapshot after iteration `it` of a solve (X, HX, rr_theta current)
 int harvest_snapshot(lobpcg_ctx *ctx, int k, lobpcg_harvest *h, hipStream_t s);
 // gamma and the per-row network features from both views of the strict upper triangle

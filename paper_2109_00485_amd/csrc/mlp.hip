@@ -133,7 +133,11 @@ __device__ inline float bounded_scale_fast(float o) {
 }
 
 // W = m o R with m_ij = exp(b(o_ij)) / s(d_i - sigma_j), sigma_j the diagonal
-// preconditioner's shift of column j; R may alias W.
+// preconditioner's shift of column j; R may alias W.  An entry whose learned
+// factor is not finite gets the diagonal step alone (counted in *fallbacks
+// when that is given).  Inside a solve, flags stops the kernel when the
+// iteration's Cholesky QR or Rayleigh-Ritz failed (W then still holds the
+// projected block the retry starts from).
 // KP > 0 fixes k at compile time (the sample -> (row, column) split is a shift).
 // The next step's inputs are loaded before this step's matrix-core work, so
 // every wave keeps one step of loads in flight.
@@ -143,8 +147,11 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int
                                                                   const float *__restrict__ rho,
                                                                   const float *__restrict__ tmean,
                                                                   const double *__restrict__ theta, const T *R, T *W,
-                                                                  double eps, double off) {
+                                                                  double eps, double off, const int *__restrict__ flags,
+                                                                  unsigned long long *__restrict__ fallbacks) {
+    if (flags && (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL))) return;
     const int lane = threadIdx.x % LOBPCG_WAVE, c = lane % 16, g = lane / 16;
+    unsigned nfb = 0;
     const int k = KP ? KP : k_rt;
     LaneWeights L;
     load_lane_weights(L, P, c, g);
@@ -191,16 +198,27 @@ __global__ __launch_bounds__(INF_THREADS) void mlp_precond_kernel(int64_t n, int
                 // reciprocal (a few ulp; the guard decision stays in FP64)
                 const float rs = __builtin_amdgcn_rcpf((float)sg);
                 float m = bounded_scale_fast(o) * rs;
-                if (!isfinite(m)) m = rs;
+                if (!isfinite(m)) {
+                    m = rs;
+                    ++nfb;
+                }
                 W[sidx] = cur.r * m;
             } else {
                 const float e = expf(OUT_BOUND * tanhf(o / OUT_BOUND));
                 double m = (double)e / sg;
-                if (!isfinite(m)) m = 1.0 / sg;
+                if (!isfinite(m)) {
+                    m = 1.0 / sg;
+                    ++nfb;
+                }
                 W[sidx] = cur.r * m;
             }
         }
         cur = nxt;
+    }
+    if (fallbacks) {
+        // one integer atomic per wave (a count: the order does not matter)
+        for (int off2 = 32; off2 > 0; off2 >>= 1) nfb += __shfl_xor(nfb, off2);
+        if (lane == 0 && nfb) atomicAdd(fallbacks, (unsigned long long)nfb);
     }
 }
 
@@ -648,14 +666,17 @@ int mlp_precond_ready(lobpcg_ctx *ctx) {
     return LOBPCG_OK;
 }
 
-int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s) {
+int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s,
+                       bool in_solve) {
+    const int *flags = in_solve ? ctx->dflags : nullptr;
+    unsigned long long *fb = in_solve ? ctx->mlp_fallback_count : nullptr;
     const double eps = ctx->eps_rel * ctx->gamma;
     const int grid = inference_grid(ctx->n * k);
 #define MLP_LAUNCH(T, KP)                                                                                 \
     mlp_precond_kernel<T, KP><<<grid, INF_THREADS, 0, s>>>(ctx->n, k, ctx->mlp->params, (const T *)ctx->diag, \
                                                            ctx->feat_rownorm, ctx->feat_tilemean, theta,     \
                                                            (const T *)R, (T *)W, eps,  \
-                                                           ctx->precond_offset)
+                                                           ctx->precond_offset, flags, fb)
     if (ctx->dtype == LOBPCG_F32) {
         if (k == 8) MLP_LAUNCH(float, 8);
         else if (k == 16) MLP_LAUNCH(float, 16);

@@ -18,7 +18,7 @@
 
 #include "internal.hpp"
 
-int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s);
+int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s, int force = 0);
 
 namespace {
 
@@ -76,10 +76,22 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     const bool timing = info && info->timing;
     Timer tm{ctx, s, timing};
     double t_spmm = 0, t_upd = 0, t_gram = 0, t_rr = 0, t_orth = 0;
-    int n_spmm = 0, p_dropped = 0, retries = 0, confirmations = 0, refreshes = 0;
+    int n_spmm = 0, p_dropped = 0, retries = 0, confirmations = 0, refreshes = 0, shifted = 0;
+    // failure branches forced from the host (lobpcg_set_test_faults): device bits
+    // for attempt `attempt` of iteration `iter` (iteration 0: the initial Rayleigh-Ritz)
+    auto forced = [&](int iter, int attempt) -> int {
+        const int m = ctx->test_fault_mask;
+        if (!m || iter != ctx->test_fault_iter) return 0;
+        int f = 0;
+        if (attempt == 0 && (m & LOBPCG_FAULT_CHOLQR_SHIFT)) f |= FORCE_CHOLQR_UNSHIFTED;
+        if ((attempt == 0 && (m & LOBPCG_FAULT_CHOLQR_ONCE)) || (m & LOBPCG_FAULT_CHOLQR_ALWAYS)) f |= FORCE_CHOLQR;
+        if (m & LOBPCG_FAULT_RR_DROP_P) f |= FORCE_RR_WITH_P;
+        if (m & LOBPCG_FAULT_RR) f |= FORCE_RR;
+        return f;
+    };
     const int upd_precond = precond == LOBPCG_PRECOND_MLP ? LOBPCG_PRECOND_NONE : precond;
     auto apply_mlp = [&]() -> int {
-        if (precond == LOBPCG_PRECOND_MLP) return launch_mlp_precond(ctx, ctx->W, ctx->rr_theta, ctx->W, k, s);
+        if (precond == LOBPCG_PRECOND_MLP) return launch_mlp_precond(ctx, ctx->W, ctx->rr_theta, ctx->W, k, s, true);
         return LOBPCG_OK;
     };
     auto gram_rr_input = [&](int nb) -> int {
@@ -104,7 +116,8 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     } while (0)
 
     HIP_TRY(ctx, hipMemcpyAsync(ctx->X, Xuser, blk, hipMemcpyDeviceToDevice, s));
-    TRY(launch_set_flags(ctx, 0, 0, s));
+    TRY(launch_fill_zero(ctx->mlp_fallback_count, sizeof(unsigned long long), s));
+    TRY(launch_set_flags(ctx, 0, 0, s, forced(0, 0)));
     tm.mark(0);
     // Algorithm 1, start: Rayleigh-Ritz on X0
     TRY(launch_spmm(ctx, ctx->X, ctx->HX, k, s));
@@ -163,9 +176,9 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
         }
         if (it >= maxiter) break;
         ++it;
-        bool done_iter = false;
-        for (int attempt = 0; attempt < 2 && !done_iter; ++attempt) {
-            TRY(launch_set_flags(ctx, 0, 0, s));
+        bool done_iter = false, rr_failed = false;
+        for (int attempt = 0; attempt < 2 && !done_iter && !rr_failed; ++attempt) {
+            TRY(launch_set_flags(ctx, 0, 0, s, forced(it, attempt)));
             tm.mark(0);
             // W <- W - X (X^T W), then Cholesky QR
             {
@@ -205,12 +218,16 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             t_orth += tm.span(0, 1); t_spmm += tm.span(1, 2); t_gram += tm.span(2, 3);
             t_rr += tm.span(3, 4); t_upd += tm.span(4, 5);
             if (fl & FLAG_RR_FAIL) {
-                return set_err(ctx, LOBPCG_ENOTSPD, "Rayleigh-Ritz failed at iteration %d", it);
+                // X, HX and P are untouched by the skipped update: the last iterate is returned
+                rr_failed = true;
+                break;
             }
             if (fl & FLAG_RR_PDROP) ++p_dropped;
+            if (fl & FLAG_CHOLQR_SHIFT) ++shifted;
             have_p = true;
             done_iter = true;
         }
+        if (rr_failed) { status = set_err(ctx, LOBPCG_ENOTSPD, "Rayleigh-Ritz failed at iteration %d", it); break; }
         if (!done_iter) { status = set_err(ctx, LOBPCG_ENOTSPD, "Cholesky QR failed twice at iteration %d", it); break; }
         if (ctx->refresh_every && it % ctx->refresh_every == 0) {
             // the recurrences eqs. upd1-upd2 drift in FP32: recompute H X and H P
@@ -249,6 +266,8 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     }
 #undef TRY
     HIP_TRY(ctx, hipMemcpyAsync(Xuser, ctx->X, blk, hipMemcpyDeviceToDevice, s));
+    unsigned long long fallbacks = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&fallbacks, ctx->mlp_fallback_count, sizeof fallbacks, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     rel_from_report(ctx, k, tau, rel.data(), &finite);
     for (int j = 0; j < k; ++j) {
@@ -262,6 +281,8 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
         info->cholqr_retries = retries;
         info->confirmations = confirmations;
         info->refreshes = refreshes;
+        info->cholqr_shifted = shifted;
+        info->mlp_fallbacks = (long long)fallbacks;
         info->status = status;
         info->gamma = ctx->gamma;
         info->t_spmm = t_spmm;

@@ -239,3 +239,21 @@ def from_dense_upper(A: np.ndarray, dtype=None) -> ArrayCSR:
                 col.append(j); val.append(A[i, j])
         rp.append(len(col))
     return ArrayCSR(n, rp, col, np.asarray(val, dtype=dtype or A.dtype), desc=f"dense({n})")
+
+
+def near_diagonal(n: int = 2000, draws: int = 10, seed: int = 3, coupling: float = 0.01, dtype=np.float64) -> ArrayCSR:
+    """Diagonal 1.0, 1.1, 1.2, ... plus weak random couplings N(0,1) * coupling
+    between each row and `draws` random partners (pairs summed): eigenvalues
+    ~0.1 apart, each close to one diagonal entry."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    r = np.repeat(np.arange(n), draws)
+    c = rng.integers(0, n, n * draws)
+    keep = r != c
+    i, j = np.minimum(r, c)[keep], np.maximum(r, c)[keep]
+    v = rng.standard_normal(i.size) * coupling
+    U = sp.coo_matrix((v, (i, j)), shape=(n, n)).tocsr()
+    U.sum_duplicates()
+    U = (U + sp.diags(1.0 + 0.1 * np.arange(n))).tocsr()
+    U.sort_indices()
+    return ArrayCSR(n, U.indptr, U.indices, U.data.astype(dtype), desc=f"near_diagonal({n})")

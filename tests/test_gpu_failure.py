@@ -1,0 +1,203 @@
+"""The solver's failure branches on the GPU (Section 3.5 Cholesky QR with its
+shifted fallback and one re-projected retry; the Rayleigh-Ritz step dropping
+P; LOBPCG_ENOTSPD when neither helps), forced from the host with
+lobpcg_set_test_faults so that every kernel still runs to its normal end,
+plus the errors reachable without forcing: a starting block with repeated
+columns, an allocation beyond device memory, and a learned network whose
+factor is not finite (each such entry falls back to the diagonal step).
+The converged runs are held to the dense spectrum."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import to_dev, torch_cuda, upload
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+_LAM = {}
+
+
+def dense_lowest(A, nev=5):
+    if "rs1k" not in _LAM:
+        H = oracle.SymMatrix.from_csr(A)
+        _LAM["rs1k"] = (np.linalg.eigvalsh(H @ np.eye(A.n)), 1e-3 * H.gershgorin())
+    lam, tau = _LAM["rs1k"]
+    return lam[:nev], tau
+
+
+def solve_with_faults(mask, iteration, f32=False, precond=None, ctx=None, **kw):
+    import paper_2109_00485_amd as L
+    torch_cuda()
+    A = W.make_matrix("random_sym_1k")
+    if ctx is None:
+        ctx = upload(A, f32)
+    ctx.set_test_faults(mask, iteration)
+    dt = np.float32 if f32 else np.float64
+    X = to_dev(W.initial_block(A.n, 8, seed=1), dt)
+    r = ctx.solve(X, 5, tol=3e-6 if f32 else 1e-6, maxiter=3000, raise_on_error=False,
+                  precond=L.PRECOND_DIAG if precond is None else precond, **kw)
+    ctx.set_test_faults(0, 0)
+    return A, ctx, r, X.cpu().numpy().astype(np.float64)
+
+
+def converged_to_spectrum(A, r, Xg):
+    lam, tau = dense_lowest(A)
+    assert r.status == 0, r.status
+    assert np.all(np.abs(r.evals[:5] - lam) <= 1e-6 * np.maximum(np.abs(lam), tau)), (r.evals[:5], lam)
+    G = Xg.T @ Xg
+    assert np.abs(G - np.eye(8)).max() < 2e-5
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_shifted_cholesky_qr(f32):
+    import paper_2109_00485_amd as L
+    A, ctx, r, Xg = solve_with_faults(L.FAULT_CHOLQR_SHIFT, 3, f32)
+    assert r.cholqr_shifted == 1 and r.cholqr_retries == 0
+    converged_to_spectrum(A, r, Xg)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_cholesky_qr_retry(f32):
+    import paper_2109_00485_amd as L
+    A, ctx, r, Xg = solve_with_faults(L.FAULT_CHOLQR_ONCE, 3, f32)
+    assert r.cholqr_retries == 1
+    converged_to_spectrum(A, r, Xg)
+
+
+def test_rayleigh_ritz_drops_p():
+    import paper_2109_00485_amd as L
+    A, ctx, r, Xg = solve_with_faults(L.FAULT_RR_DROP_P, 5)
+    assert r.p_dropped == 1
+    converged_to_spectrum(A, r, Xg)
+
+
+@pytest.mark.parametrize("mask,iteration", [("always", 3), ("rr", 4), ("rr", 0)])
+def test_unrecoverable_failures_return_enotspd(mask, iteration):
+    import paper_2109_00485_amd as L
+    m = {"always": L.FAULT_CHOLQR_ALWAYS, "rr": L.FAULT_RR}[mask]
+    A, ctx, r, Xg = solve_with_faults(m, iteration)
+    assert r.status == L.ENOTSPD
+    if iteration > 0:
+        # the last accepted iterate comes back: orthonormal, finite
+        assert np.all(np.isfinite(Xg)) and np.abs(Xg.T @ Xg - np.eye(8)).max() < 1e-8
+        assert r.iters == iteration
+    # the context is usable afterwards (faults off)
+    X = to_dev(W.initial_block(A.n, 8, seed=1), np.float64)
+    r2 = ctx.solve(X, 5, tol=1e-6, maxiter=3000)
+    converged_to_spectrum(A, r2, X.cpu().numpy())
+
+
+def test_fault_mask_validation():
+    import paper_2109_00485_amd as L
+    torch_cuda()
+    ctx = upload(W.make_matrix("random_sym_1k"), False)
+    with pytest.raises(L.LobpcgError) as e:
+        ctx.set_test_faults(64, 1)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.LobpcgError):
+        ctx.set_test_faults(L.FAULT_RR, -1)
+
+
+def test_repeated_columns_in_x0():
+    """X0 with two equal columns: the first Rayleigh-Ritz pencil is singular, the
+    solve returns LOBPCG_ENOTSPD (the oracle raises on the same block)."""
+    import paper_2109_00485_amd as L
+    torch_cuda()
+    A = W.make_matrix("random_sym_1k")
+    X0 = W.initial_block(A.n, 8, seed=1)
+    X0[:, 3] = X0[:, 1]
+    ctx = upload(A, False)
+    r = ctx.solve(to_dev(X0, np.float64), 5, raise_on_error=False)
+    assert r.status == L.ENOTSPD
+    from oracle.lobpcg import lobpcg as oracle_lobpcg
+    from oracle.dense import NotSPD
+    with pytest.raises(NotSPD):
+        oracle_lobpcg(oracle.SymMatrix.from_csr(A), X0, 5, d=A.diag)
+
+
+def test_create_beyond_device_memory_returns_enomem():
+    """A context whose six n x 16 FP64 blocks need about twice the free device
+    memory (the matrix itself: one diagonal entry per row, ~5% of it):
+    LOBPCG_ENOMEM, nothing left allocated, and a small context still works
+    afterwards."""
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    torch.cuda.empty_cache()
+    free0, total = torch.cuda.mem_get_info()
+    n = min((1 << 31) - 64, int(2.2 * free0 / (6 * 16 * 8)))
+    print(f"free {free0 / 2**30:.1f} GiB of {total / 2**30:.1f} GiB; n = {n}")
+    rp = torch.arange(n + 1, dtype=torch.int64, device="cuda")        # one (diagonal) entry per row
+    col = torch.arange(n, dtype=torch.int32, device="cuda")
+    val = torch.ones(n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    with pytest.raises(L.LobpcgError) as e:
+        L.Context(n, rp, col, val, dtype=L.F64, kmax=16)
+    assert e.value.status == L.ENOMEM
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free1 - (256 << 20)       # the partial allocations were released
+    del rp, col, val
+    torch.cuda.empty_cache()
+    A = W.make_matrix("random_sym_1k")
+    ctx = upload(A, False)
+    r = ctx.solve(to_dev(W.initial_block(A.n, 8, seed=1), np.float64), 5)
+    assert r.status == 0
+
+
+def net_blob(nan_output=False):
+    """A network whose factor is exactly 1 (all weights zero), or one whose
+    output is NaN for every input while every weight is finite: features
+    shifted to be positive, first and second layers of +1e38 (the hidden
+    activations overflow to +inf), and an output layer of alternating signs
+    (inf - inf)."""
+    import paper_2109_00485_amd as L
+    p = {name: np.zeros(shape, dtype=np.float32) for name, shape in L.MLP_LAYOUT}
+    p["sigma"] = np.ones(4, dtype=np.float32)
+    if nan_output:
+        p["mu"] = np.full(4, -1000.0, dtype=np.float32)
+        p["W1"] = np.full((64, 4), 1e38, dtype=np.float32)
+        p["W2"] = np.full((64, 64), 1e38, dtype=np.float32)
+        p["w3"] = np.where(np.arange(64) % 2 == 0, 1.0, -1.0).astype(np.float32)
+    return L.pack_params(p)
+
+
+def test_nonfinite_network_falls_back_to_diagonal():
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    A = W.make_matrix("random_sym_1k")
+    lam, tau = dense_lowest(A)
+    ctx = upload(A, False)
+    net = L.Mlp(net_blob(nan_output=True))
+    ctx.set_mlp(net)
+    X = to_dev(W.initial_block(A.n, 8, seed=1), np.float64)
+    rm = ctx.solve(X, 5, tol=1e-6, maxiter=3000, precond=L.PRECOND_MLP)
+    # every application of the network fell back on every entry
+    assert rm.mlp_fallbacks == A.n * 8 * (1 + rm.iters + rm.cholqr_retries + rm.confirmations)
+    X = to_dev(W.initial_block(A.n, 8, seed=1), np.float64)
+    rd = ctx.solve(X, 5, tol=1e-6, maxiter=3000, precond=L.PRECOND_DIAG)
+    assert rd.mlp_fallbacks == 0
+    # so the learned solve is the diagonal one (up to the rounding of 1/s versus a division)
+    assert abs(rm.iters - rd.iters) <= 2
+    for r in (rm, rd):
+        assert np.all(np.abs(r.evals[:5] - lam) <= 1e-6 * np.maximum(np.abs(lam), tau))
+
+
+def test_mlp_retry_starts_from_the_projected_block():
+    """After a failed Cholesky QR the learned preconditioner is not applied a
+    second time to the block the retry re-projects: with a network whose
+    factor is exactly 1 the learned solve follows the diagonal solve through a
+    forced retry (applied twice, the factor 1/s would change the retried block
+    completely)."""
+    import paper_2109_00485_amd as L
+    torch = torch_cuda()
+    A = W.make_matrix("random_sym_1k")
+    ctx = upload(A, False)
+    net = L.Mlp(net_blob())
+    ctx.set_mlp(net)
+    hist = {}
+    for name, pc in (("diag", L.PRECOND_DIAG), ("mlp", L.PRECOND_MLP)):
+        _, _, r, _ = solve_with_faults(L.FAULT_CHOLQR_ONCE, 3, precond=pc, ctx=ctx, history=True)
+        assert r.status == 0 and r.cholqr_retries == 1
+        hist[name] = r.theta_hist
+    np.testing.assert_allclose(hist["mlp"][:6], hist["diag"][:6], rtol=1e-6)

@@ -67,7 +67,15 @@ def test_random_sym_1k(f32):
         assert np.all(np.diff(th, axis=0) <= 1e-12 * r.gamma)
         # same steps as the oracle: the first iterations' Ritz values agree closely
         # (near-degenerate early Ritz values amplify rounding differences later on)
-        np.testing.assert_allclose(th[:2], np.array(ref.theta_hist[:2]), rtol=1e-10)
+        rth = np.array(ref.theta_hist)
+        m = min(len(th), len(rth))
+        agree = np.all(np.abs(th[:m] - rth[:m]) <= 1e-10 * np.abs(rth[:m]), axis=1)
+        print(f"theta histories agree to 1e-10 for the first {int(np.argmin(agree)) if not agree.all() else m} "
+              f"of {m} iterations")
+        # the same steps as the oracle (both scale the Rayleigh-Ritz pencil to a unit
+        # diagonal of O): the first iterations agree to 1e-10; later, near-degenerate
+        # early Ritz values amplify the two paths' different summation orders
+        np.testing.assert_allclose(th[:4], rth[:4], rtol=1e-10)
     else:
         th = r.theta_hist
         assert np.all(np.diff(th, axis=0) <= 1e-6 * r.gamma)
@@ -229,3 +237,54 @@ def test_maxiter_and_argument_errors():
         with pytest.raises(L.LobpcgError) as e:
             ctx.solve(X, **kw)
         assert e.value.status == L.EINVAL
+
+
+def test_theta_history_matches_oracle_on_separated_spectrum():
+    """Every iteration's Ritz values of the FP64 GPU solve against the oracle's,
+    on a matrix whose wanted eigenvalues are well separated (there the two
+    paths' rounding differences are not amplified, unlike the clustered early
+    Ritz values of the random workloads), with the diagonal step's shift 4
+    Ritz-value spreads below theta_j.  Bar 1e-9 relative: the GPU's Gram
+    products sum in a different order than the oracle's (~1e-13 relative per
+    product), and 22 iterations carry that to ~1e-10."""
+    A = synth.near_diagonal(2000)
+    H, ref = oracle_solve("sep2k", A, precond_offset=4.0)
+    assert ref.status == 0
+    import paper_2109_00485_amd as L
+    ctx = upload(A, False)
+    ctx.set_precond_offset(4.0)
+    X = to_dev(W.initial_block(A.n, 8, seed=1), np.float64)
+    r = ctx.solve(X, 5, history=True, maxiter=200)
+    Xg = X.cpu().numpy()
+    assert r.status == 0, r
+    check_against_oracle(H, ref, r, Xg, False)
+    th = r.theta_hist
+    ref_th = np.array(ref.theta_hist)
+    m = min(len(th), len(ref_th))
+    print(f"{len(th)} GPU / {len(ref_th)} oracle iterations")
+    assert m >= 3 and abs(len(th) - len(ref_th)) <= 1
+    np.testing.assert_allclose(th[:m], ref_th[:m], rtol=1e-9)
+
+
+def test_near_diagonal_shift_at_theta_stays_in_the_spectrum():
+    """The diagonal step with its shift at theta_j on a nearly diagonal matrix
+    drives the Rayleigh-Ritz basis toward dependence; the step must drop P
+    rather than accept a nearly singular O (whose reduced pencil gives Ritz
+    values below the lowest eigenvalue).  FP64: every Ritz value of the
+    history stays at or above lambda_min and the solve converges to the dense
+    spectrum.  (FP32 blocks cannot resolve this basis: there the shift held
+    4 Ritz-value spreads below theta_j converges, as on every workload.)"""
+    import paper_2109_00485_amd as L
+    A = synth.near_diagonal(2000)
+    H = oracle.SymMatrix.from_csr(A)
+    lam = np.linalg.eigvalsh(H @ np.eye(A.n))
+    for f32, off in ((False, 0.0), (True, 4.0)):
+        ctx = upload(A, f32)
+        ctx.set_precond_offset(off)
+        X = to_dev(W.initial_block(A.n, 8, seed=1), np.float32 if f32 else np.float64)
+        r = ctx.solve(X, 5, history=True, maxiter=3000, tol=3e-6 if f32 else 1e-6)
+        assert r.status == 0, (f32, r.status, r.iters)
+        assert r.theta_hist.min() >= lam[0] - (1e-6 if f32 else 1e-12) * r.gamma, r.theta_hist.min()
+        tau = 1e-3 * r.gamma
+        assert np.all(np.abs(r.evals[:5] - lam[:5]) <= 1e-6 * np.maximum(np.abs(lam[:5]), tau))
+        print(f"f32={f32} offset {off}: {r.iters} iterations, P dropped {r.p_dropped} times")

@@ -150,3 +150,42 @@ def test_precond_offset_solve_vs_dense_eigh(offset):
     np.testing.assert_allclose(r.theta, lam, rtol=1e-9)
     np.testing.assert_allclose(r.X_all.T @ r.X_all, np.eye(8), atol=1e-10)
     assert r.iters < r0.iters, (r.iters, r0.iters)
+
+
+def test_near_diagonal_shift_at_theta_keeps_ritz_values_in_the_spectrum():
+    """Nearly diagonal H with the diagonal step's shift at theta_j: the basis
+    [X, W, P] drifts toward dependence and the Rayleigh-Ritz Gram O becomes
+    nearly singular (scaled pivots ~1e-14 here).  Accepting such an O gives
+    Ritz values below the lowest eigenvalue (Courant-Fischer forbids them for
+    an exact projection); the oracle drops P instead and converges to the
+    dense spectrum."""
+    A = synth.near_diagonal(2000)
+    H = oracle.SymMatrix.from_csr(A)
+    lam = np.linalg.eigvalsh(H @ np.eye(A.n))
+    r = lobpcg(H, W.initial_block(A.n, 8, seed=1), 5, d=A.diag, maxiter=2000)
+    assert r.status == OK
+    assert r.p_dropped > 0
+    assert np.min(np.array(r.theta_hist)) >= lam[0] - 1e-12 * H.gershgorin()
+    np.testing.assert_allclose(r.theta, lam[:5], rtol=1e-8)
+
+
+def test_rayleigh_ritz_rejects_a_nearly_singular_basis():
+    """Two basis columns at an angle of 1e-6 (scaled Gram pivot ~1e-12): the
+    Rayleigh-Ritz step reports a non-SPD O; at an angle of 1e-3 (pivot 1e-6) it
+    proceeds and its Ritz values lie inside the spectrum of H."""
+    from oracle.dense import NotSPD, assemble_pencil, rayleigh_ritz
+    rng = np.random.default_rng(4)
+    n = 50
+    M = rng.standard_normal((n, n))
+    Hd = M + M.T
+    lam = np.linalg.eigvalsh(Hd)
+    for angle, ok in ((1e-6, False), (1e-3, True)):
+        S = rng.standard_normal((n, 3))
+        S[:, 2] = S[:, 1] + angle * np.linalg.norm(S[:, 1]) * rng.standard_normal(n) / np.sqrt(n)
+        G, O = assemble_pencil([S], [Hd @ S])
+        if ok:
+            th, C = rayleigh_ritz(G, O, 3)
+            assert np.all(th >= lam[0] - 1e-9) and np.all(th <= lam[-1] + 1e-9)
+        else:
+            with pytest.raises(NotSPD):
+                rayleigh_ritz(G, O, 3)
