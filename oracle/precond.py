@@ -45,6 +45,13 @@ def diag_precond(R: np.ndarray, d: np.ndarray, theta: np.ndarray, eps: float, of
 # space K_m(A, b) and the Hessenberg matrix H_m, and the approximate solution
 # is x = V_m y with H_m y = ||b|| e_1.  Each column of R is its own right-hand
 # side with its own shift (multiple Krylov spaces, Section 3.4).
+# Each new Arnoldi vector is orthogonalised twice (two modified Gram-Schmidt
+# passes, their coefficients summed into H_m; "twice is enough").  The paper
+# does not fix the Gram-Schmidt variant; a single pass loses orthogonality
+# completely on a shifted tile dominated by a constant diagonal (A = c I + E
+# with |E| << c, the typical tile of a matrix with sorted diagonal): every
+# A v_j is nearly parallel to v_j, and after a few steps V_m is no longer a
+# basis, so the single-pass "FOM iterate" is rounding noise.
 
 FOM_BREAKDOWN = 1e-12   # h_{j+1,j} <= this * ||A v_j||: K_j is invariant, x is exact
 FOM_SINGULAR = 1e-12    # min |R_ii| <= this * max |h_ij| (H_m = QR, h over H_{m+1,m}): no FOM iterate
@@ -69,13 +76,15 @@ def diagonal_tiles(n: int, row_ptr, col, val, tile: int = 64) -> np.ndarray:
     return out
 
 
-def fom(A: np.ndarray, b: np.ndarray, m: int):
+def fom(A: np.ndarray, b: np.ndarray, m: int, basis: bool = False):
     """m steps of FOM on A x = b from x = 0.  Returns (x, ok); ok is False when
-    H_m is singular to working precision (then there is no FOM iterate)."""
+    H_m is singular to working precision (then there is no FOM iterate).  With
+    ``basis``, also the Arnoldi basis V_s and the square Hessenberg H_s of the
+    s <= m steps taken (s < m after an invariant Krylov space)."""
     b = np.asarray(b, dtype=np.float64)
     beta = np.linalg.norm(b)
     if beta == 0.0:
-        return np.zeros_like(b), True
+        return (np.zeros_like(b), True) + ((np.zeros((b.size, 0)), np.zeros((0, 0))) if basis else ())
     N = b.size
     V = np.zeros((N, m + 1))
     Hm = np.zeros((m + 1, m))
@@ -84,22 +93,25 @@ def fom(A: np.ndarray, b: np.ndarray, m: int):
     for j in range(m):
         w = A @ V[:, j]
         wnorm = np.linalg.norm(w)
-        for i in range(j + 1):
-            Hm[i, j] = w @ V[:, i]
-            w = w - Hm[i, j] * V[:, i]
+        for _ in range(2):
+            for i in range(j + 1):
+                h = w @ V[:, i]
+                Hm[i, j] += h
+                w = w - h * V[:, i]
         Hm[j + 1, j] = np.linalg.norm(w)
         if Hm[j + 1, j] <= FOM_BREAKDOWN * wnorm:
             steps = j + 1
             break
         V[:, j + 1] = w / Hm[j + 1, j]
     Hs = Hm[:steps, :steps]
+    extra = (V[:, :steps].copy(), Hs.copy()) if basis else ()
     rdiag = np.abs(np.diag(np.linalg.qr(Hs, mode="r")))
     if rdiag.min() <= FOM_SINGULAR * np.abs(Hm[:steps + 1, :steps]).max():
-        return np.zeros_like(b), False
+        return (np.zeros_like(b), False) + extra
     e1 = np.zeros(steps)
     e1[0] = beta
     y = np.linalg.solve(Hs, e1)
-    return V[:, :steps] @ y, True
+    return (V[:, :steps] @ y, True) + extra
 
 
 def block_fom_precond(tiles: np.ndarray, R: np.ndarray, theta: np.ndarray, m: int, eps: float,

@@ -2,7 +2,9 @@
 FOM run for as many steps as the tile has rows is the exact tile solve; one
 step has a closed form; the residual after m steps is orthogonal to the
 Krylov space (the Galerkin condition that defines FOM), checked against a
-basis built independently; an eigenvector right-hand side ends the Arnoldi
+basis built independently; the Arnoldi basis is orthonormal and projects A
+onto H_m also on a tile dominated by a constant diagonal (where a single
+Gram-Schmidt pass loses the basis); an eigenvector right-hand side ends the Arnoldi
 process after one step with the exact solution; 1 x 1 tiles reproduce the
 diagonal step; the dense diagonal tiles reassemble H."""
 import numpy as np
@@ -51,6 +53,24 @@ def test_residual_orthogonal_to_krylov_space(m):
     assert np.abs(Q.T @ r).max() <= 1e-10 * np.linalg.norm(b)
     # and x lies in that space
     assert np.linalg.norm(x - Q @ (Q.T @ x)) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_arnoldi_basis_orthonormal_on_a_far_shifted_tile():
+    """The Arnoldi process builds an orthonormal basis V_m with V_m^T A V_m =
+    H_m.  On a diagonal tile of a block-sparse matrix shifted far below its
+    spectrum (A = c I + E, |E| << c) every A v_j is nearly parallel to v_j; a
+    single Gram-Schmidt pass loses the orthogonality of V_m there (V^T V off
+    the identity by ~1) and this fails."""
+    H = synth.tiled(64 * 40, tile=64, tile_draws=5, p=0.1, seed=2, f32=False)
+    tiles = diagonal_tiles(H.n, H.row_ptr, H.col, H.val)
+    A = tiles[5] + 1232.0 * np.eye(64)
+    b = synth.gaussian_block(H.n, 8, seed=5)[5 * 64:6 * 64, 0]
+    x, ok, V, Hs = fom(A, b, 8, basis=True)
+    assert ok and V.shape == (64, 8)
+    assert np.abs(V.T @ V - np.eye(8)).max() <= 1e-13
+    assert np.abs(V.T @ A @ V - Hs).max() <= 1e-12 * np.abs(A).max()
+    # and the Galerkin condition on the iterate
+    assert np.abs(V.T @ (b - A @ x)).max() <= 1e-12 * np.linalg.norm(b)
 
 
 def test_eigenvector_right_hand_side_is_solved_in_one_step():
