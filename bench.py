@@ -181,6 +181,8 @@ def main():
                     help="skip the learned-vs-diagonal preconditioner comparison")
     ap.add_argument("--learned-seeds", default="1000:1006",
                     help="evaluation matrices (seeds) of the learned-preconditioner workload")
+    ap.add_argument("--fom-steps", type=lambda v: [int(x) for x in v.split(",") if x], default=[2],
+                    help="FOM steps of the block-diagonal preconditioner runs (empty: skip them)")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only time the sparse product (profiling runs); prints one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -334,6 +336,45 @@ def main():
                              weights=os.path.relpath(wpath, ROOT), trained_on_seeds=meta.get("train_seeds"),
                              offset=float(meta.get("offset", 0.0)))
         log(f"learned preconditioner on this matrix: status {rl.status} iters {rl.iters} {solve_learned['seconds']} s")
+    # the paper's block-diagonal preconditioner (Section 3.4): the 64 x 64 diagonal
+    # tiles shifted per column, m FOM steps; standalone apply (HIP events, same
+    # stream) and solves with the shift at theta_j and --offset spreads below
+    solve_fom, fom_apply = [], None
+    if args.fom_steps:
+        theta_d = torch.from_numpy(np.asarray(last.evals, dtype=np.float64)).cuda()
+        Wf = torch.empty_like(X0)
+        fom_bytes = ((A.n + 63) // 64) * 64 * 64 * esz + 2 * A.n * args.k * esz
+        fom_apply = {"bytes_per_launch": int(fom_bytes)}
+        for m in args.fom_steps:
+            ctx.set_fom_steps(m)
+            for _ in range(3):
+                ctx.precond_apply(X0, theta_d, Wf, kind=L.PRECOND_FOM)
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record()
+            for _ in range(args.spmm_reps):
+                ctx.precond_apply(X0, theta_d, Wf, kind=L.PRECOND_FOM)
+            f1.record()
+            torch.cuda.synchronize()
+            fms = f0.elapsed_time(f1) / args.spmm_reps
+            fom_apply[f"m{m}_ms"] = round(fms, 4)
+            fom_apply[f"m{m}_GBps"] = round(fom_bytes / fms / 1e6, 1)
+            log(f"FOM apply m={m}: {fms:.3f} ms ({fom_bytes / fms / 1e6:.0f} GB/s of tiles + R + W)")
+            for off in sorted({0.0, args.offset}):
+                ctx.set_precond_offset(off)
+                rf, secs = None, []
+                for rep in range(1 + args.steps):
+                    Xf = X0.clone()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    rf = ctx.solve(Xf, args.nev, tol=args.tol, maxiter=args.maxiter, precond=L.PRECOND_FOM)
+                    torch.cuda.synchronize()
+                    if rep:
+                        secs.append(time.perf_counter() - t0)
+                solve_fom.append(dict(m=m, offset=off, seconds=round(float(np.mean(secs)), 4), iters=rf.iters,
+                                      status=rf.status, evals=[float(x) for x in rf.evals[:args.nev]]))
+                log(f"FOM m={m} offset {off}: status {rf.status} iters {rf.iters} {solve_fom[-1]['seconds']} s")
+        ctx.set_precond_offset(0.0)
+        ctx.set_fom_steps(4)
     # the iteration count from a random start depends on rounding (the shifted
     # diagonal preconditioner is nearly singular while theta is far above the
     # wanted eigenvalues): report solves from a few other Gaussian starts too
@@ -368,6 +409,8 @@ def main():
         "solve_other_starts": other_starts,
         "solve_offset": solve_offset,
         "solve_learned": solve_learned,
+        "solve_fom": solve_fom,
+        "fom_apply": fom_apply,
         "spmm_standalone_ms": round(spmm_ms, 4),
         "spmm_in_solve_ms": round(spmm_in_solve_ms, 4),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -55,6 +55,7 @@ extern "C" {
 #define LOBPCG_PRECOND_NONE 0    /* K = I                                       */
 #define LOBPCG_PRECOND_DIAG 1    /* W_ij = R_ij / s(d_i - sigma_j), sigma_j = theta_j by default */
 #define LOBPCG_PRECOND_MLP  2    /* learned scaling from an attached MLP        */
+#define LOBPCG_PRECOND_FOM  3    /* shifted 64 x 64 diagonal tiles of H, FOM     */
 
 #define LOBPCG_FORMAT_AUTO  0    /* tiled when tiles are dense enough, else CSR */
 #define LOBPCG_FORMAT_CSR   1    /* row-split CSR of the strict upper triangle  */
@@ -141,7 +142,10 @@ int lobpcg_spmm_sym(lobpcg_ctx *ctx, const void *X, void *Y, int k, void *stream
  * with c the context's offset (lobpcg_set_precond_offset; default 0, i.e. the
  * shift is the Ritz value theta_j itself), s(x) = x if |x| >= eps else +-eps
  * (sign of x, + for 0), eps = eps_rel * gamma.  With LOBPCG_PRECOND_MLP the
- * attached network supplies a factor on that step (lobpcg_set_mlp).
+ * attached network supplies a factor on that step (lobpcg_set_mlp).  With
+ * LOBPCG_PRECOND_FOM, K is block diagonal, its blocks the 64 x 64 diagonal
+ * tiles of H shifted by the same sigma_j, each system solved by m FOM steps
+ * (lobpcg_set_fom_steps).
  *   R      device, n x k row-major
  *   theta  device, double[k]
  *   W      device, n x k row-major, written (may alias R)
@@ -171,6 +175,22 @@ int lobpcg_precond_apply(lobpcg_ctx *ctx, const void *R, const double *theta, vo
 #define LOBPCG_FAULT_RR_DROP_P     8
 #define LOBPCG_FAULT_RR            16
 int lobpcg_set_test_faults(lobpcg_ctx *ctx, int mask, int iteration);
+
+/*
+ * lobpcg_set_fom_steps -- FOM steps of LOBPCG_PRECOND_FOM, 1 <= m <= 8
+ * (default 4; the paper uses three to five).  That preconditioner is the
+ * block-diagonal K of Section 3.4: K_t = H_tt - sigma_j I, H_tt the t-th
+ * 64 x 64 diagonal tile of H (rows t*64 .. t*64+63; the last tile is ragged),
+ * sigma_j the diagonal step's shift of column j (lobpcg_set_precond_offset);
+ * each (tile, column) system K_t w = r is solved by m steps of the full
+ * orthogonalisation method (Arnoldi with modified Gram-Schmidt, w = V_m y,
+ * H_m y = ||r|| e_1, stopping early on an invariant Krylov space), in FP64 for
+ * either context precision; where H_m is singular to 1e-12 of its largest
+ * entry, that column of that tile gets the guarded diagonal step.  The dense
+ * tiles (n * 64 values) are built at create.  Returns LOBPCG_EINVAL outside
+ * [1, 8].  Host-only; takes effect on the next launch.
+ */
+int lobpcg_set_fom_steps(lobpcg_ctx *ctx, int m);
 
 /*
  * lobpcg_set_precond_offset -- place the diagonal preconditioner's shift c

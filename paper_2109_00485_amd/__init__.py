@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblobpcg.so")
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F64 = 1, 2
 GRAM_AUTO, GRAM_F64, GRAM_F32, GRAM_BF16X3 = 0, 1, 2, 3
-PRECOND_NONE, PRECOND_DIAG, PRECOND_MLP = 0, 1, 2
+PRECOND_NONE, PRECOND_DIAG, PRECOND_MLP, PRECOND_FOM = 0, 1, 2, 3
 FORMAT_AUTO, FORMAT_CSR, FORMAT_TILED = 0, 1, 2
 
 
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_mlp_last_error.argtypes = [P]
     lib.lobpcg_set_mlp.restype = cint
     lib.lobpcg_set_mlp.argtypes = [P, P]
+    lib.lobpcg_set_fom_steps.restype = cint
+    lib.lobpcg_set_fom_steps.argtypes = [P, cint]
     lib.lobpcg_set_test_faults.restype = cint
     lib.lobpcg_set_test_faults.argtypes = [P, cint, cint]
     lib.lobpcg_set_precond_offset.restype = cint
@@ -295,6 +297,10 @@ class Context:
                                        _dev_ptr(B, self.torch_dtype, "B"), kb,
                                        _dev_ptr(G, torch.float64, "G"), prec, _stream_ptr(stream)), "gram")
         return G
+
+    def set_fom_steps(self, m: int):
+        """lobpcg_set_fom_steps: FOM steps of the block-diagonal preconditioner (1..8)."""
+        self._check(load().lobpcg_set_fom_steps(self._h, int(m)), "set_fom_steps")
 
     def set_test_faults(self, mask: int, iteration: int = 1):
         """lobpcg_set_test_faults: force the solver's failure branches at one iteration (tests)."""

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblobpcg.so")
-SOURCES = ["ctx.hip", "spmm.hip", "spmm_tiled.hip", "gram.hip", "dense.hip", "update.hip", "solve.hip", "mlp.hip", "harvest.hip", "probe.hip"]
+SOURCES = ["ctx.hip", "spmm.hip", "spmm_tiled.hip", "gram.hip", "dense.hip", "update.hip", "solve.hip", "mlp.hip", "harvest.hip", "probe.hip", "fom.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

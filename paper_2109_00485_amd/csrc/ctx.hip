@@ -176,7 +176,7 @@ void free_ctx(lobpcg_ctx *c) {
     void *ptrs[] = {c->rp, c->ci, c->val, c->diag, c->cp, c->cri, c->cval, c->feat_rownorm, c->feat_tilemean, c->X, c->W, c->P,
                     c->HX, c->HW, c->HP, c->gram_partial, c->gram_out, c->gram_out2, c->rr_C, c->rr_theta,
                     c->orth_rinv, c->norm_partial, c->report_dev, c->dflags, c->tiled.data, c->tiled.woff,
-                    c->tiled.wdesc, c->tiled.wbeg, c->tiled.list, c->harvest_counter, c->mlp_fallback_count,
+                    c->tiled.wdesc, c->tiled.wbeg, c->tiled.list, c->harvest_counter, c->mlp_fallback_count, c->diag_tiles,
                     c->heavy_rows};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

@@ -102,6 +102,10 @@ struct lobpcg_ctx {
     // failure branches forced at one iteration (tests of the error paths)
     int test_fault_mask = 0, test_fault_iter = -1;
     unsigned long long *mlp_fallback_count = nullptr;   // device counter of per-entry MLP fallbacks
+    // block-diagonal preconditioner: dense symmetric 64 x 64 diagonal tiles of H
+    // (context dtype, [tile][64][64], unit diagonal past n) and its FOM step count
+    void *diag_tiles = nullptr;
+    int fom_steps = 4;
     int device = 0;
     // strict upper triangle in CSR + diagonal
     int64_t *rp = nullptr;
@@ -184,6 +188,9 @@ int launch_rayleigh_quotients(lobpcg_ctx *ctx, int k, hipStream_t s);
 int launch_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, int kind,
                    hipStream_t s);
 int mlp_precond_ready(lobpcg_ctx *ctx);
+// block-diagonal FOM preconditioner (in_solve: skip after a failed Cholesky QR / Rayleigh-Ritz)
+int launch_fom_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s,
+                       bool in_solve = false);
 // in_solve: skip after a failed Cholesky QR / Rayleigh-Ritz and count fallbacks
 int launch_mlp_precond(lobpcg_ctx *ctx, const void *R, const double *theta, void *W, int k, hipStream_t s,
                        bool in_solve = false);

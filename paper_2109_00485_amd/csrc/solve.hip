@@ -64,7 +64,8 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     if ((int64_t)3 * k > ctx->n) return set_err(ctx, LOBPCG_EINVAL, "solve: need 3k <= n");
     if (!(tol > 0)) return set_err(ctx, LOBPCG_EINVAL, "solve: tol must be > 0");
     if (maxiter < 0) return set_err(ctx, LOBPCG_EINVAL, "solve: maxiter must be >= 0");
-    if (precond != LOBPCG_PRECOND_NONE && precond != LOBPCG_PRECOND_DIAG && precond != LOBPCG_PRECOND_MLP)
+    if (precond != LOBPCG_PRECOND_NONE && precond != LOBPCG_PRECOND_DIAG && precond != LOBPCG_PRECOND_MLP &&
+        precond != LOBPCG_PRECOND_FOM)
         return set_err(ctx, LOBPCG_EINVAL, "solve: bad preconditioner %d", precond);
     if (precond == LOBPCG_PRECOND_MLP) {
         int rc = mlp_precond_ready(ctx);
@@ -89,9 +90,11 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
         if (m & LOBPCG_FAULT_RR) f |= FORCE_RR;
         return f;
     };
-    const int upd_precond = precond == LOBPCG_PRECOND_MLP ? LOBPCG_PRECOND_NONE : precond;
-    auto apply_mlp = [&]() -> int {
+    // the learned and the block-diagonal preconditioners act on W = R after the update
+    const int upd_precond = precond == LOBPCG_PRECOND_DIAG ? LOBPCG_PRECOND_DIAG : LOBPCG_PRECOND_NONE;
+    auto apply_after_update = [&]() -> int {
         if (precond == LOBPCG_PRECOND_MLP) return launch_mlp_precond(ctx, ctx->W, ctx->rr_theta, ctx->W, k, s, true);
+        if (precond == LOBPCG_PRECOND_FOM) return launch_fom_precond(ctx, ctx->W, ctx->rr_theta, ctx->W, k, s, true);
         return LOBPCG_OK;
     };
     auto gram_rr_input = [&](int nb) -> int {
@@ -128,7 +131,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     TRY(launch_rr(ctx, k, 1, s));
     tm.mark(3);
     TRY(launch_update(ctx, k, 1, upd_precond, 1, s));
-    TRY(apply_mlp());
+    TRY(apply_after_update());
     tm.mark(4);
     TRY(read_report(ctx, s));
     t_spmm += tm.span(0, 1); t_gram += tm.span(1, 2); t_rr += tm.span(2, 3); t_upd += tm.span(3, 4);
@@ -164,7 +167,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             TRY(launch_rayleigh_quotients(ctx, k, s));
             tm.mark(2);
             TRY(launch_update(ctx, k, 0, upd_precond, 1, s));
-            TRY(apply_mlp());
+            TRY(apply_after_update());
             tm.mark(3);
             TRY(read_report(ctx, s));
             t_spmm += tm.span(0, 1); t_gram += tm.span(1, 2); t_upd += tm.span(2, 3);
@@ -206,7 +209,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             TRY(launch_rr(ctx, k, nb, s));
             tm.mark(4);
             TRY(launch_update(ctx, k, nb, upd_precond, 1, s));
-            TRY(apply_mlp());
+            TRY(apply_after_update());
             tm.mark(5);
             TRY(read_report(ctx, s));
             const int fl = (int)ctx->report_host->flags;
@@ -238,7 +241,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             ++refreshes;
             tm.mark(1);
             TRY(launch_update(ctx, k, 0, upd_precond, 1, s));
-            TRY(apply_mlp());
+            TRY(apply_after_update());
             tm.mark(2);
             TRY(read_report(ctx, s));
             t_spmm += tm.span(0, 1); t_upd += tm.span(1, 2);

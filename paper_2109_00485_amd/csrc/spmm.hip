@@ -270,6 +270,26 @@ int build_csc(lobpcg_ctx *ctx, hipStream_t s) {
                                     hipMemcpyHostToDevice, s));
     }
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    {
+        // dense symmetric 64 x 64 diagonal tiles for the block-diagonal preconditioner
+        const int64_t NT = (n + 63) / 64;
+        std::vector<T> d(n);
+        HIP_TRY(ctx, hipMemcpy(d.data(), ctx->diag, n * sizeof(T), hipMemcpyDeviceToHost));
+        std::vector<T> tiles((size_t)NT * 64 * 64, T(0));
+        for (int64_t i = 0; i < NT * 64; ++i) {
+            T *tl = &tiles[(size_t)(i / 64) * 4096];
+            const int a = (int)(i % 64);
+            tl[a * 64 + a] = i < n ? d[i] : T(1);
+            if (i >= n) continue;
+            for (int64_t e = rp[i]; e < rp[i + 1] && ci[e] / 64 == i / 64; ++e) {
+                const int b = ci[e] % 64;
+                tl[a * 64 + b] = val[e];
+                tl[b * 64 + a] = val[e];
+            }
+        }
+        HIP_TRY(ctx, hipMalloc(&ctx->diag_tiles, tiles.size() * sizeof(T)));
+        HIP_TRY(ctx, hipMemcpy(ctx->diag_tiles, tiles.data(), tiles.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
     if (ctx->format_request == LOBPCG_FORMAT_CSR) return LOBPCG_OK;
 
     // tiled format (window stream of both views); the 32-bit-index arrays are

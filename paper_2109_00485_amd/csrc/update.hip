@@ -351,7 +351,8 @@ extern "C" int lobpcg_precond_apply(lobpcg_ctx *ctx, const void *R, const double
     if (!ctx) return LOBPCG_EINVAL;
     if (!R || !theta || !W) return set_err(ctx, LOBPCG_EINVAL, "precond_apply: null pointer");
     if (k < 1 || k > ctx->kmax) return set_err(ctx, LOBPCG_EINVAL, "precond_apply: k=%d outside [1,%d]", k, ctx->kmax);
-    if (kind != LOBPCG_PRECOND_NONE && kind != LOBPCG_PRECOND_DIAG && kind != LOBPCG_PRECOND_MLP)
+    if (kind != LOBPCG_PRECOND_NONE && kind != LOBPCG_PRECOND_DIAG && kind != LOBPCG_PRECOND_MLP &&
+        kind != LOBPCG_PRECOND_FOM)
         return set_err(ctx, LOBPCG_EINVAL, "precond_apply: bad kind %d", kind);
     hipStream_t s = (hipStream_t)stream;
     int rc;
@@ -359,6 +360,8 @@ extern "C" int lobpcg_precond_apply(lobpcg_ctx *ctx, const void *R, const double
         rc = mlp_precond_ready(ctx);
         if (rc != LOBPCG_OK) return rc;
         rc = launch_mlp_precond(ctx, R, theta, W, k, s);
+    } else if (kind == LOBPCG_PRECOND_FOM) {
+        rc = launch_fom_precond(ctx, R, theta, W, k, s);
     } else {
         rc = launch_precond(ctx, R, theta, W, k, kind, s);
     }
