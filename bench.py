@@ -117,6 +117,33 @@ def learned_vs_diag(args):
     return out
 
 
+def host_info():
+    """The host the CPU baseline ran on: model, logical CPUs, CPUs this process
+    may use, and RAM (from /proc; the box's own figures, not this build's)."""
+    info = {"logical_cpus": os.cpu_count()}
+    try:
+        info["usable_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    info["ram_GiB"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
 def cpu_baseline(A, k, budget_s=15.0, iters_sample=6):
     import oracle
     from synth import workloads as W
@@ -151,11 +178,19 @@ def cpu_baseline(A, k, budget_s=15.0, iters_sample=6):
                   callback=lambda it, *a: marks.append(time.perf_counter()))
     t_end = time.perf_counter()
     per_iter = (t_end - marks[0]) / max(len(marks), 1) if marks else None
+    full = None
+    if A.n <= 100_000:
+        # small matrices: the oracle's whole solve, timed
+        t = time.perf_counter()
+        ro = oracle_lobpcg(H, X, 5, tol=1e-6, maxiter=5000, d=A.diag)
+        full = dict(seconds=round(time.perf_counter() - t, 3), iters=ro.iters,
+                    evals=[float(v) for v in ro.theta[:5]])
     return dict(value=round(gbs, 3), unit="GB/s", cores=cores, kind="oracle",
                 sample=f"{len(times)} FP64 oracle sparse products (two-pass, OpenMP) of the full matrix, "
                        f"median {per * 1e3:.1f} ms each; {len(marks)} iterations of the FP64 oracle LOBPCG "
                        f"(diagonal step, shift at theta_j) from the bench's start",
                 single_thread_value=round(algorithmic_bytes(A.n, A.nnz, k) / per1 / 1e9, 3),
+                host=host_info(), solve=full,
                 solve_s_per_iteration=None if per_iter is None else round(per_iter, 3))
 
 
@@ -224,6 +259,24 @@ def main():
     torch.cuda.synchronize()
     spmm_ms = s0.elapsed_time(s1) / args.spmm_reps
     log(f"standalone spmm: {spmm_ms:.3f} ms, {nbytes / spmm_ms / 1e6:.1f} GB/s")
+    # the same product with a block of 16 vectors (the second block width of the workload)
+    spmm16 = None
+    if args.k != 16 and ctx.kmax >= 16:
+        X16 = torch.from_numpy(W.initial_block(A.n, 16, seed=1, dtype=np.float32 if f32 else np.float64)).cuda()
+        Y16 = torch.empty_like(X16)
+        for _ in range(3):
+            ctx.spmm_sym(X16, Y16)
+        s0.record()
+        for _ in range(args.spmm_reps):
+            ctx.spmm_sym(X16, Y16)
+        s1.record()
+        torch.cuda.synchronize()
+        ms16 = s0.elapsed_time(s1) / args.spmm_reps
+        b16 = algorithmic_bytes(A.n, A.nnz, 16, esz)
+        spmm16 = {"k": 16, "ms": round(ms16, 4), "GBps": round(b16 / ms16 / 1e6, 1),
+                  "frac": round(b16 / ms16 / 1e6 / HBM_PEAK_GBS, 4), "bytes_per_launch": int(b16)}
+        log(f"standalone spmm k=16: {ms16:.3f} ms, {b16 / ms16 / 1e6:.1f} GB/s")
+        del X16, Y16
     copy_gbs = read_gbs = None
     if not args.spmm_only:
         # achievable HBM bandwidth on this GPU: the library's plain streaming
@@ -412,6 +465,7 @@ def main():
         "solve_fom": solve_fom,
         "fom_apply": fom_apply,
         "spmm_standalone_ms": round(spmm_ms, 4),
+        "spmm_k16": spmm16,
         "spmm_in_solve_ms": round(spmm_in_solve_ms, 4),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),

@@ -121,6 +121,17 @@ void lobpcg_opts_default(lobpcg_opts *o);
 int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr, const int32_t *col,
                   const void *val, const lobpcg_opts *opts, void *stream);
 
+/*
+ * lobpcg_create_rp32 -- lobpcg_create with int32 row offsets (row_ptr
+ * device, int32[n+1]; so nnz < 2^31).  The offsets are widened into a
+ * temporary int64 device array (8(n+1) bytes, freed before return), then
+ * lobpcg_create runs on it; same validation, results and errors, plus
+ * LOBPCG_ENOMEM when the temporary cannot be allocated.  A negative or
+ * decreasing offset is caught by the validation pass (LOBPCG_EINVAL).
+ */
+int lobpcg_create_rp32(lobpcg_ctx **out, int64_t n, const int32_t *row_ptr, const int32_t *col,
+                       const void *val, const lobpcg_opts *opts, void *stream);
+
 void lobpcg_destroy(lobpcg_ctx *ctx);
 
 /*

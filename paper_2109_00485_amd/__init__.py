@@ -86,6 +86,8 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_opts_default.argtypes = [ctypes.POINTER(Opts)]
     lib.lobpcg_create.restype = cint
     lib.lobpcg_create.argtypes = [ctypes.POINTER(P), i64, P, P, P, ctypes.POINTER(Opts), P]
+    lib.lobpcg_create_rp32.restype = cint
+    lib.lobpcg_create_rp32.argtypes = [ctypes.POINTER(P), i64, P, P, P, ctypes.POINTER(Opts), P]
     lib.lobpcg_destroy.restype = None
     lib.lobpcg_destroy.argtypes = [P]
     lib.lobpcg_spmm_sym.restype = cint
@@ -214,9 +216,12 @@ class Context:
         o.dtype, o.gram, o.format, o.kmax = dtype, gram, fmt, kmax
         o.tau_rel, o.eps_rel = tau_rel, eps_rel
         h = ctypes.c_void_p()
-        rc = lib.lobpcg_create(ctypes.byref(h), int(n), _dev_ptr(row_ptr, torch.int64, "row_ptr"),
-                               _dev_ptr(col, torch.int32, "col"), _dev_ptr(val, tval, "val"), ctypes.byref(o),
-                               _stream_ptr(stream))
+        # int32 row offsets go through lobpcg_create_rp32, int64 through lobpcg_create
+        create, rpt = ((lib.lobpcg_create_rp32, torch.int32) if row_ptr.dtype == torch.int32
+                       else (lib.lobpcg_create, torch.int64))
+        rc = create(ctypes.byref(h), int(n), _dev_ptr(row_ptr, rpt, "row_ptr"),
+                    _dev_ptr(col, torch.int32, "col"), _dev_ptr(val, tval, "val"), ctypes.byref(o),
+                    _stream_ptr(stream))
         if rc != OK:
             raise LobpcgError(rc, lib.lobpcg_strerror(rc).decode())
         self._h = h
@@ -228,9 +233,11 @@ class Context:
 
     @classmethod
     def from_csr(cls, A, device="cuda", **kw):
-        """Upload an upper-triangle CSR (numpy arrays ``row_ptr, col, val``)."""
+        """Upload an upper-triangle CSR (numpy arrays ``row_ptr, col, val``);
+        int32 row offsets stay int32 (lobpcg_create_rp32), others are int64."""
         import torch
-        rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=np.int64)).to(device)
+        rpd = np.int32 if np.asarray(A.row_ptr).dtype == np.int32 else np.int64
+        rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=rpd)).to(device)
         ci = torch.from_numpy(np.ascontiguousarray(A.col, dtype=np.int32)).to(device)
         va = torch.from_numpy(np.ascontiguousarray(A.val)).to(device)
         ctx = cls(A.n, rp, ci, va, **kw)

@@ -341,6 +341,31 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
     return LOBPCG_OK;
 }
 
+namespace {
+__global__ void widen_offsets_kernel(int64_t m, const int32_t *__restrict__ in, int64_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) out[i] = in[i];
+}
+}  // namespace
+
+extern "C" int lobpcg_create_rp32(lobpcg_ctx **out, int64_t n, const int32_t *row_ptr, const int32_t *col,
+                                  const void *val, const lobpcg_opts *opts, void *stream) {
+    if (!out) return LOBPCG_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n >= (int64_t)1 << 31 || !row_ptr) return LOBPCG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t *rp64 = nullptr;
+    if (hipMalloc((void **)&rp64, (n + 1) * sizeof(int64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return LOBPCG_ENOMEM;
+    }
+    widen_offsets_kernel<<<ceil_div(n + 1, 256), 256, 0, s>>>(n + 1, row_ptr, rp64);
+    int rc = hipGetLastError() == hipSuccess ? lobpcg_create(out, n, rp64, col, val, opts, stream) : LOBPCG_EHIP;
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(rp64);
+    return rc;
+}
+
 extern "C" void lobpcg_destroy(lobpcg_ctx *ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
