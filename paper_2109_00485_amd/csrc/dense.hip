@@ -64,10 +64,11 @@ __device__ bool chol_lower(double *a, int N, double tol) {
         const double piv = a[j * LD + j];
         for (int i = j + 1 + t; i < N; i += blockDim.x) a[i * LD + j] /= piv;
         __syncthreads();
-        const int m = N - j - 1;
-        for (int e = t; e < m * m; e += blockDim.x) {
-            const int i = j + 1 + e / m, l = j + 1 + e % m;
-            if (l <= i) a[i * LD + l] -= a[i * LD + j] * a[l * LD + j];
+        // trailing lower triangle over a 16-column thread grid (no integer division)
+        const int tr = t / 16, tc = t % 16, TR = blockDim.x / 16;
+        for (int i = j + 1 + tr; i < N; i += TR) {
+            const double aij = a[i * LD + j];
+            for (int l = j + 1 + tc; l <= i; l += 16) a[i * LD + l] -= aij * a[l * LD + j];
         }
         __syncthreads();
     }
@@ -140,8 +141,8 @@ __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__rest
 // round number, so its loads of A, V and of the rotations are independent.
 constexpr int RR_THREADS = 256;
 constexpr int NPAIR = NMAX / 2;
-constexpr int RR_BLK = (NPAIR * (NPAIR + 1) / 2 + RR_THREADS - 1) / RR_THREADS;   // blocks per thread
-constexpr int RR_VROW = (NMAX * NPAIR + RR_THREADS - 1) / RR_THREADS;            // V items per thread
+// Jacobi units per thread: A blocks (a <= b) and V blocks of the largest pencil
+constexpr int RR_UNITS = (NPAIR * (NPAIR + 1) / 2 + NPAIR * NPAIR + RR_THREADS - 1) / RR_THREADS;
 
 __device__ inline double block_total(double v, double *sh) {
     v = wave_sum(v);
@@ -180,31 +181,35 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
     __shared__ double sc[NMAX];
     __shared__ int idx[NMAX];
     __shared__ double pr_c[NPAIR], pr_s[NPAIR];
+    __shared__ short2 ptab[NMAX - 1][NPAIR];
     __shared__ double sh[RR_THREADS / LOBPCG_WAVE];
     __shared__ double Ys[NMAX * KM_CHOL];
     const int t = threadIdx.x;
     if (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL)) return;
     const int KA = nblk_in * k, KB = 2 * KA;
     int nblk = nblk_in;
+    // a 16-column thread grid for the entry-wise loops (no integer division)
+    const int tr = t / 16, tc = t % 16, TR = RR_THREADS / 16;
     for (;;) {
         const int N = nblk * k;
         // pencil from lower blocks; diagonal blocks symmetrised
-        for (int e = t; e < N * N; e += RR_THREADS) {
-            int a = e / N, b = e % N, ba = a / k, bb = b / k;
-            double o, g;
-            if (ba > bb) {
-                o = M[a * KB + b];
-                g = M[a * KB + KA + b];
-            } else if (ba < bb) {
-                o = M[b * KB + a];
-                g = M[b * KB + KA + a];
-            } else {
-                o = 0.5 * (M[a * KB + b] + M[b * KB + a]);
-                g = 0.5 * (M[a * KB + KA + b] + M[b * KB + KA + a]);
+        for (int a = tr; a < N; a += TR)
+            for (int b = tc; b < N; b += 16) {
+                const int ba = (a >= k) + (a >= 2 * k), bb = (b >= k) + (b >= 2 * k);
+                double o, g;
+                if (ba > bb) {
+                    o = M[a * KB + b];
+                    g = M[a * KB + KA + b];
+                } else if (ba < bb) {
+                    o = M[b * KB + a];
+                    g = M[b * KB + KA + a];
+                } else {
+                    o = 0.5 * (M[a * KB + b] + M[b * KB + a]);
+                    g = 0.5 * (M[a * KB + KA + b] + M[b * KB + KA + a]);
+                }
+                O[a * LD + b] = o;
+                A[a * LD + b] = g;
             }
-            O[a * LD + b] = o;
-            A[a * LD + b] = g;
-        }
         __syncthreads();
         if (t < N) {
             double d = O[t * LD + t];
@@ -213,11 +218,11 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
         __syncthreads();
         bool posdiag = true;
         for (int i = 0; i < N; ++i) posdiag = posdiag && sc[i] > 0;
-        for (int e = t; e < N * N; e += RR_THREADS) {
-            int a = e / N, b = e % N;
-            O[a * LD + b] *= sc[a] * sc[b];
-            A[a * LD + b] *= sc[a] * sc[b];
-        }
+        for (int a = tr; a < N; a += TR)
+            for (int b = tc; b < N; b += 16) {
+                O[a * LD + b] *= sc[a] * sc[b];
+                A[a * LD + b] *= sc[a] * sc[b];
+            }
         __syncthreads();
         const int force = flags[2];
         bool ok = posdiag && chol_lower(O, N, tol) && !(force & FORCE_RR) && !(nblk == 3 && (force & FORCE_RR_WITH_P));
@@ -231,65 +236,88 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
             if (t == 0) atomicOr(&flags[0], FLAG_RR_FAIL);
             return;
         }
-        // Z = L^{-1} G (column c per thread), stored in V
-        for (int c = t; c < N; c += RR_THREADS) {
-            for (int i = 0; i < N; ++i) {
-                double v = A[i * LD + c];
-                for (int p = 0; p < i; ++p) v -= O[i * LD + p] * V[p * LD + c];
-                V[i * LD + c] = v / O[i * LD + i];
-            }
+        // Z = L^{-1} G, then A = L^{-1} Z^T (= L^{-1} G L^{-T}, G symmetric), both by
+        // right-looking forward substitution over a 16-column thread grid: at step p
+        // row p is divided by L_pp, then every later row subtracts L_ip times it, so
+        // each entry receives its updates in the order p = 0, 1, ... and no thread
+        // runs a long dependent chain
+        {
+            auto forward = [&](double *Z) {
+                for (int p = 0; p < N; ++p) {
+                    for (int c = t; c < N; c += RR_THREADS) Z[p * LD + c] /= O[p * LD + p];
+                    __syncthreads();
+                    for (int i = p + 1 + tr; i < N; i += TR) {
+                        const double lip = O[i * LD + p];
+                        for (int c = tc; c < N; c += 16) Z[i * LD + c] -= lip * Z[p * LD + c];
+                    }
+                    __syncthreads();
+                }
+            };
+            for (int i = tr; i < N; i += TR)
+                for (int c = tc; c < N; c += 16) V[i * LD + c] = A[i * LD + c];
+            __syncthreads();
+            forward(V);
+            for (int i = tr; i < N; i += TR)
+                for (int c = tc; c < N; c += 16) A[i * LD + c] = V[c * LD + i];
+            __syncthreads();
+            forward(A);
         }
-        __syncthreads();
-        // A = L^{-1} Z^T  (= L^{-1} G L^{-T} since G is symmetric)
-        for (int c = t; c < N; c += RR_THREADS) {
-            for (int i = 0; i < N; ++i) {
-                double v = V[c * LD + i];
-                for (int p = 0; p < i; ++p) v -= O[i * LD + p] * A[p * LD + c];
-                A[i * LD + c] = v / O[i * LD + i];
-            }
-        }
-        __syncthreads();
         // symmetrise (both triangles from their average), V = I
-        for (int e = t; e < N * N; e += RR_THREADS) {
-            const int i = e / N, j = e % N;
-            const double v = i == j ? A[i * LD + j] : 0.5 * (A[i * LD + j] + A[j * LD + i]);
-            V[i * LD + j] = i == j ? 1.0 : 0.0;
-            if (i >= j) {
-                A[i * LD + j] = v;
-                A[j * LD + i] = v;
+        for (int i = tr; i < N; i += TR)
+            for (int j = tc; j < N; j += 16) {
+                V[i * LD + j] = i == j ? 1.0 : 0.0;
+                if (i > j) {
+                    const double v = 0.5 * (A[i * LD + j] + A[j * LD + i]);
+                    A[i * LD + j] = v;
+                    A[j * LD + i] = v;
+                }
             }
-        }
         __syncthreads();
         // cyclic Jacobi, round-robin pairing over Ne = N rounded up to even
-        // (index N, if present, is a dummy whose rotation is the identity)
-        const int Ne = N + (N & 1), NP = Ne / 2, NB = NP * (NP + 1) / 2;
-        // this thread's blocks (a <= b) and V items (row, pair), fixed for all rounds
-        int ba[RR_BLK], bb[RR_BLK], vi[RR_VROW], vb[RR_VROW];
+        // (index N, if present, is a dummy whose rotation is the identity).  The
+        // pairs of every round are tabulated once; a round's work is a list of
+        // units, each one 2 x 2 block of A (pairs a <= b) or of V (row pair a,
+        // column pair b), at most two per thread, so a thread's instructions per
+        // round are few and the same for all rounds.
+        const int Ne = N + (N & 1), NP = Ne / 2, NB = NP * (NP + 1) / 2, NU = NB + NP * NP;
+        for (int e = t; e < (Ne - 1) * NP; e += RR_THREADS) {
+            const int r = e / NP, a = e % NP;
+            int p, q;
+            rr_pair(a, r, Ne, p, q);
+            ptab[r][a] = make_short2((short)p, (short)q);
+        }
+        // this thread's units (u < NB: A block (a, b), a <= b; else V block), fixed for all rounds
+        int ua[RR_UNITS], ub[RR_UNITS];
+        bool uv[RR_UNITS];
 #pragma unroll
-        for (int m = 0; m < RR_BLK; ++m) {
-            const int e = t + RR_THREADS * m;
-            int a = 0, rem = e;
-            while (rem >= NP - a && a < NP) {
-                rem -= NP - a;
-                ++a;
+        for (int m = 0; m < RR_UNITS; ++m) {
+            const int u = t + RR_THREADS * m;
+            int a = -1, b = 0;
+            if (u < NB) {
+                int rem = u;
+                a = 0;
+                while (rem >= NP - a) {
+                    rem -= NP - a;
+                    ++a;
+                }
+                b = a + rem;
+            } else if (u < NU) {
+                a = (u - NB) / NP;
+                b = (u - NB) % NP;
             }
-            ba[m] = e < NB ? a : -1;
-            bb[m] = a + rem;
+            ua[m] = a;
+            ub[m] = b;
+            uv[m] = u >= NB;
         }
-#pragma unroll
-        for (int m = 0; m < RR_VROW; ++m) {
-            const int e = t + RR_THREADS * m;
-            vi[m] = e < N * NP ? e / NP : -1;
-            vb[m] = e % NP;
-        }
+        __syncthreads();
         for (int sweep = 0; sweep < 30; ++sweep) {
             double off = 0.0, tot = 0.0;
-            for (int e = t; e < N * N; e += RR_THREADS) {
-                const int i = e / N, j = e % N;
-                const double v = A[i * LD + j];
-                tot += v * v;
-                if (i != j) off += v * v;
-            }
+            for (int i = tr; i < N; i += TR)
+                for (int j = tc; j < N; j += 16) {
+                    const double v = A[i * LD + j];
+                    tot += v * v;
+                    if (i != j) off += v * v;
+                }
             off = block_total(off, sh);
             tot = block_total(tot, sh);
             // stop at an off-diagonal norm of 1e-13 of the matrix norm: below that the
@@ -297,8 +325,8 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
             if (off <= 1e-26 * tot || off == 0.0) break;
             for (int r = 0; r < Ne - 1; ++r) {
                 if (t < NP) {
-                    int p, q;
-                    rr_pair(t, r, Ne, p, q);
+                    const short2 pq = ptab[r][t];
+                    const int p = pq.x, q = pq.y;
                     // tan of the angle that annihilates a_pq: the root of smaller
                     // magnitude of t^2 + 2 t (a_qq - a_pp) / (2 a_pq) - 1 = 0
                     double c = 1.0, sn = 0.0;
@@ -317,16 +345,28 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
                     pr_s[t] = sn;
                 }
                 __syncthreads();
-                // A <- J^T A J by blocks: new column p = c p - s q, new column q = s p + c q
 #pragma unroll
-                for (int m = 0; m < RR_BLK; ++m) {
-                    if (ba[m] < 0) continue;
-                    const int a = ba[m], b = bb[m];
-                    int p1, q1, p2, q2;
-                    rr_pair(a, r, Ne, p1, q1);
-                    rr_pair(b, r, Ne, p2, q2);
+                for (int m = 0; m < RR_UNITS; ++m) {
+                    if (ua[m] < 0) continue;
+                    const short2 pa = ptab[r][ua[m]], pb = ptab[r][ub[m]];
+                    const int p1 = pa.x, q1 = pa.y, p2 = pb.x, q2 = pb.y;
                     const bool v1 = q1 < N, v2 = q2 < N;
-                    const double c1 = pr_c[a], s1 = pr_s[a], c2 = pr_c[b], s2 = pr_s[b];
+                    const double c2 = pr_c[ub[m]], s2 = pr_s[ub[m]];
+                    if (uv[m]) {
+                        // V <- V J on rows p1, q1 and the column pair (p2, q2)
+                        if (!v2) continue;   // a dummy column pair: the identity
+                        const double x11 = V[p1 * LD + p2], x12 = V[p1 * LD + q2];
+                        const double x21 = v1 ? V[q1 * LD + p2] : 0.0, x22 = v1 ? V[q1 * LD + q2] : 0.0;
+                        V[p1 * LD + p2] = c2 * x11 - s2 * x12;
+                        V[p1 * LD + q2] = s2 * x11 + c2 * x12;
+                        if (v1) {
+                            V[q1 * LD + p2] = c2 * x21 - s2 * x22;
+                            V[q1 * LD + q2] = s2 * x21 + c2 * x22;
+                        }
+                        continue;
+                    }
+                    // A <- J^T A J on the block: new column p = c p - s q, new column q = s p + c q
+                    const double c1 = pr_c[ua[m]], s1 = pr_s[ua[m]];
                     const double x11 = A[p1 * LD + p2];
                     const double x12 = v2 ? A[p1 * LD + q2] : 0.0;
                     const double x21 = v1 ? A[q1 * LD + p2] : 0.0;
@@ -335,7 +375,7 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
                     const double y21 = c2 * x21 - s2 * x22, y22 = s2 * x21 + c2 * x22;
                     const double z11 = c1 * y11 - s1 * y21, z21 = s1 * y11 + c1 * y21;
                     const double z12 = c1 * y12 - s1 * y22, z22 = s1 * y12 + c1 * y22;
-                    if (a == b) {
+                    if (ua[m] == ub[m]) {
                         // the rotated pair: its off-diagonal entry is annihilated
                         A[p1 * LD + p1] = z11;
                         if (v1) {
@@ -360,20 +400,6 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
                         }
                     }
                 }
-                // V <- V J, one (row, pair) per item
-#pragma unroll
-                for (int m = 0; m < RR_VROW; ++m) {
-                    if (vi[m] < 0) continue;
-                    const int i = vi[m], b = vb[m];
-                    int p, q;
-                    rr_pair(b, r, Ne, p, q);
-                    if (q < N) {
-                        const double c = pr_c[b], sn = pr_s[b];
-                        const double vp = V[i * LD + p], vq = V[i * LD + q];
-                        V[i * LD + p] = c * vp - sn * vq;
-                        V[i * LD + q] = sn * vp + c * vq;
-                    }
-                }
                 __syncthreads();
             }
         }
@@ -388,17 +414,25 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
             idx[rank] = i0;
         }
         __syncthreads();
-        // C = diag(sc) L^{-T} V[:, idx[0..k)]
-        if (t < k) {
-            const int col = idx[t];
-            double *y = Ys + t;   // column t of Ys, stride KM_CHOL
+        // C = diag(sc) L^{-T} V[:, idx[0..k)]: right-looking back substitution over
+        // a 16-column thread grid (row i is divided by L_ii, then every earlier row
+        // subtracts L_ip times it)
+        {
+            for (int i = tr; i < N; i += TR)
+                for (int c = tc; c < k; c += 16) Ys[i * KM_CHOL + c] = V[i * LD + idx[c]];
+            __syncthreads();
             for (int i = N - 1; i >= 0; --i) {
-                double v = V[i * LD + col];
-                for (int p = i + 1; p < N; ++p) v -= O[p * LD + i] * y[p * KM_CHOL];
-                y[i * KM_CHOL] = v / O[i * LD + i];
+                for (int c = t; c < k; c += RR_THREADS) Ys[i * KM_CHOL + c] /= O[i * LD + i];
+                __syncthreads();
+                for (int p = tr; p < i; p += TR) {
+                    const double lip = O[i * LD + p];
+                    for (int c = tc; c < k; c += 16) Ys[p * KM_CHOL + c] -= lip * Ys[i * KM_CHOL + c];
+                }
+                __syncthreads();
             }
-            for (int i = 0; i < N; ++i) Cout[i * k + t] = sc[i] * y[i * KM_CHOL];
-            theta[t] = A[col * LD + col];
+            for (int i = tr; i < N; i += TR)
+                for (int c = tc; c < k; c += 16) Cout[i * k + c] = sc[i] * Ys[i * KM_CHOL + c];
+            if (t < k) theta[t] = A[idx[t] * LD + idx[t]];
         }
         if (t == 0) flags[1] = nblk;
         return;
