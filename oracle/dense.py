@@ -1,6 +1,7 @@
 """FP64 dense steps of LOBPCG (test infrastructure; see the package docstring).
 
-Cholesky QR (paper Section 3.5):  B = W^T W,  B = R^T R,  W <- W R^{-1}.
+Cholesky QR (paper Section 3.5):  B = W^T W,  B = R^T R,  W <- W R^{-1};
+CholeskyQR2 repeats it once on the result.
 Gram blocks (eq. Glower): only the lower blocks of G = S^T H S and
 O = S^T S are formed; each upper block is the transpose of its lower
 counterpart, and each diagonal block is averaged with its own transpose.
@@ -63,6 +64,17 @@ def cholqr(W: np.ndarray, shift: float | None = None) -> tuple[np.ndarray, np.nd
         R = Rp / s[None, :]
     Q = sla.solve_triangular(R, np.asarray(W, dtype=np.float64).T, trans="T", lower=False).T
     return Q, R
+
+
+def cholqr2(W: np.ndarray, shift: float | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """CholeskyQR2 (Fukaya, Nakatsukasa, Yanagisawa, Yamamoto 2014): Cholesky QR
+    applied twice, W = Q (R2 R1).  The first pass (shifted when ``shift`` is
+    given) leaves Q1 with orthogonality error of order eps cond(W)^2; the
+    second pass, on the well-conditioned Q1, brings it to order eps.  Raises
+    NotSPD when either Gram matrix is not positive definite."""
+    Q1, R1 = cholqr(W, shift=shift)
+    Q, R2 = cholqr(Q1)
+    return Q, R2 @ R1
 
 
 def assemble_pencil(S: list[np.ndarray], HS: list[np.ndarray]) -> tuple[np.ndarray, np.ndarray]:

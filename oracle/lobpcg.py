@@ -27,6 +27,14 @@ Readings where the paper is silent (each is shared by the HIP path):
   * if O = S^T S is not positive definite, P is dropped for that iteration;
   * the preconditioner is the diagonal shift-inverse (oracle.precond) unless a
     callable is supplied.
+Options for the FP32-robustness row (Section 3.5; eqs. upd1-upd2 drift):
+  * cholqr_passes=2: every Cholesky QR of W is CholeskyQR2 (a second pass on
+    its result);
+  * soft_lock=True: a column whose relative residual was at or below tol at
+    the last check is locked: its residual direction W_j and its P_j leave
+    the search space (S = [X, W_active, P_active]) while X_j stays in the
+    Rayleigh-Ritz basis, so converged columns stop feeding noise into W and
+    P; a locked column is released when its residual rises above tol again.
 Status codes match the library: 0 OK, -4 not SPD, -5 not converged.
 """
 from __future__ import annotations
@@ -38,7 +46,7 @@ import numpy as np
 from threadpoolctl import threadpool_limits
 
 from . import SymMatrix
-from .dense import NotSPD, assemble_pencil, cholqr, gram, rayleigh_ritz
+from .dense import NotSPD, assemble_pencil, cholqr, cholqr2, gram, rayleigh_ritz
 from .precond import diag_precond
 
 OK, ENOTSPD, ENOCONV = 0, -4, -5
@@ -60,6 +68,7 @@ class Result:
     p_dropped: int = 0
     cholqr_shifts: int = 0
     cholqr_retries: int = 0          # Cholesky QRs retried after projecting W again
+    active_hist: list = field(default_factory=list)   # active (unlocked) columns per iteration
 
 
 def rel_residuals(R: np.ndarray, X: np.ndarray, theta: np.ndarray, tau: float) -> np.ndarray:
@@ -71,19 +80,23 @@ def rel_residuals(R: np.ndarray, X: np.ndarray, theta: np.ndarray, tau: float) -
 def lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: int = 5000,
            precond: Optional[Callable] = "diag", d: Optional[np.ndarray] = None,
            tau_rel: float = 1e-3, eps_rel: float = 1e-5,
-           callback: Optional[Callable] = None, precond_offset: float = 0.0) -> Result:
+           callback: Optional[Callable] = None, precond_offset: float = 0.0, cholqr_passes: int = 1,
+           soft_lock: bool = False) -> Result:
     """See :func:`_lobpcg`.  Small problems run the dense BLAS single-threaded
     (thread start-up dominates there); the arithmetic is unchanged."""
+    args = (H, X0, nev, tol, maxiter, precond, d, tau_rel, eps_rel, callback, precond_offset, cholqr_passes,
+            soft_lock)
     if X0.shape[0] < 200_000:
         with threadpool_limits(1, user_api="blas"):
-            return _lobpcg(H, X0, nev, tol, maxiter, precond, d, tau_rel, eps_rel, callback, precond_offset)
-    return _lobpcg(H, X0, nev, tol, maxiter, precond, d, tau_rel, eps_rel, callback, precond_offset)
+            return _lobpcg(*args)
+    return _lobpcg(*args)
 
 
 def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: int = 5000,
             precond: Optional[Callable] = "diag", d: Optional[np.ndarray] = None,
             tau_rel: float = 1e-3, eps_rel: float = 1e-5,
-            callback: Optional[Callable] = None, precond_offset: float = 0.0) -> Result:
+            callback: Optional[Callable] = None, precond_offset: float = 0.0, cholqr_passes: int = 1,
+            soft_lock: bool = False) -> Result:
     """Lowest ``nev`` eigenpairs of H from the starting block X0 (n x k, k >= nev).
 
     ``precond``: "diag" (needs ``d``, the diagonal of H; its shift lies
@@ -95,6 +108,9 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
     n, k = X0.shape
     if not (1 <= nev <= k and 3 * k <= n):
         raise ValueError("need 1 <= nev <= k and 3k <= n")
+    if cholqr_passes not in (1, 2):
+        raise ValueError("cholqr_passes must be 1 or 2")
+    qr = cholqr2 if cholqr_passes == 2 else cholqr
     gamma = H.gershgorin()
     tau = tau_rel * gamma
     eps = eps_rel * gamma
@@ -140,10 +156,21 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
         if it >= maxiter:
             break
         it += 1
+        # soft locking: the columns converged at this check leave W and P
+        active = rel > tol if soft_lock else np.ones(k, dtype=bool)
+        res.active_hist.append(int(active.sum()))
         # preconditioned residual W = K^{-1} R
-        W = np.asarray(apply_k(R, theta, X), dtype=np.float64)
+        W = np.asarray(apply_k(R, theta, X), dtype=np.float64)[:, active]
+        if P is not None:
+            P, HP = P[:, active], HP[:, active]
+            if P.shape[1] == 0:
+                P = HP = None
         if callback is not None:
             callback(it, X, R, theta, W)
+        if W.shape[1] == 0:
+            # every column locked (possible only with soft_lock before the
+            # confirmation): the basis cannot grow, stop as not converged
+            break
         # orthogonalise against X, then Cholesky QR (Section 3.5); a shifted
         # Cholesky QR is the fallback when W^T W is numerically singular
         # (if the shifted one fails too, W is projected once more and both are
@@ -152,11 +179,11 @@ def _lobpcg(H: SymMatrix, X0: np.ndarray, nev: int, tol: float = 1e-6, maxiter: 
         orthonormal = False
         for attempt in range(2):
             try:
-                W, _ = cholqr(W)
+                W, _ = qr(W)
                 orthonormal = True
             except NotSPD:
                 try:
-                    W, _ = cholqr(W, shift=1e-12)
+                    W, _ = qr(W, shift=1e-12)
                     res.cholqr_shifts += 1
                     orthonormal = True
                 except NotSPD:

@@ -108,3 +108,43 @@ def test_shifted_cholqr():
     Q1, _ = cholqr(W2)
     Q2, _ = cholqr(W2, shift=1e-12)
     np.testing.assert_allclose(Q1, Q2, atol=1e-10)
+
+
+def _conditioned(n, k, cond, seed):
+    """n x k matrix with singular values spaced geometrically from 1 to 1/cond."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    V, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    return (U * np.geomspace(1.0, 1.0 / cond, k)) @ V.T
+
+
+def test_cholqr2_orthogonality_and_factor():
+    """CholeskyQR2 (Fukaya et al. 2014): on W with cond(W) = 1e6 one Cholesky
+    QR leaves an orthogonality error of order eps cond^2 (here above 1e-8);
+    the second pass brings it to order eps.  W = Q R with R upper triangular."""
+    from oracle.dense import cholqr2
+    W = _conditioned(2000, 8, 1e6, seed=3)
+    Q1, _ = cholqr(W)
+    e1 = np.abs(Q1.T @ Q1 - np.eye(8)).max()
+    Q, R = cholqr2(W)
+    e2 = np.abs(Q.T @ Q - np.eye(8)).max()
+    assert e1 > 1e-8 and e2 < 1e-14, (e1, e2)
+    assert np.allclose(np.tril(R, -1), 0.0)
+    assert np.abs(Q @ R - W).max() <= 1e-14 * np.abs(W).max()
+
+
+def test_cholqr2_shifted_first_pass():
+    """At cond(W) = 1e9 (cond^2 beyond 1/eps) the plain Gram matrix is not
+    positive definite to the Cholesky factorisation; a shifted first pass and
+    a plain second one give W = Q R with Q orthonormal to 1e-11 (the shifted
+    pass leaves Q1 with a condition number of about shift^-1/2), and one more
+    plain pass (shifted CholeskyQR3, Fukaya et al. 2020) to eps."""
+    from oracle.dense import cholqr2
+    W = _conditioned(2000, 8, 1e9, seed=4)
+    with pytest.raises(NotSPD):
+        cholqr(W)
+    Q, R = cholqr2(W, shift=1e-12)
+    assert np.abs(Q.T @ Q - np.eye(8)).max() < 1e-11
+    assert np.abs(Q @ R - W).max() <= 1e-14 * np.abs(W).max()
+    Q3, _ = cholqr(Q)
+    assert np.abs(Q3.T @ Q3 - np.eye(8)).max() < 1e-14

@@ -189,3 +189,41 @@ def test_rayleigh_ritz_rejects_a_nearly_singular_basis():
         else:
             with pytest.raises(NotSPD):
                 rayleigh_ritz(G, O, 3)
+
+
+def test_cholqr2_solve_vs_dense_eigh():
+    """LOBPCG with CholeskyQR2 for W: the same eigenpairs as dense eigh, Ritz
+    values never increasing, and an iteration count close to the one-pass
+    solve's (the second pass changes W only at the rounding level here)."""
+    A = W.make_matrix("random_sym_1k")
+    H, r1 = solve(A)
+    _, r2 = solve(A, cholqr_passes=2)
+    assert r2.status == OK
+    lam = np.linalg.eigvalsh(dense(A))[:5]
+    np.testing.assert_allclose(r2.theta, lam, rtol=1e-9)
+    th = np.array(r2.theta_hist)
+    assert np.all(np.diff(th, axis=0) <= 1e-12 * H.gershgorin())
+    assert abs(r2.iters - r1.iters) <= 0.1 * r1.iters, (r1.iters, r2.iters)
+
+
+def test_soft_lock_solve():
+    """Soft locking: a column whose relative residual was <= tol at the last
+    check leaves W and P.  The solve still finds the dense eigenpairs, the
+    Ritz values never increase (X stays in every Rayleigh-Ritz basis), and the
+    W of each iteration has exactly the columns not converged at the previous
+    check (seen by the callback)."""
+    A = W.make_matrix("random_sym_1k")
+    widths = []
+    H, r = solve(A, soft_lock=True, callback=lambda it, X, R, th, Wb: widths.append(Wb.shape[1]))
+    assert r.status == OK
+    lam = np.linalg.eigvalsh(dense(A))[:5]
+    np.testing.assert_allclose(r.theta, lam, rtol=1e-9)
+    th = np.array(r.theta_hist)
+    assert np.all(np.diff(th, axis=0) <= 1e-12 * H.gershgorin())
+    assert widths == r.active_hist
+    # active widths follow the previous iteration's residuals
+    rel = np.array(r.rel_hist)
+    for i in range(1, len(widths)):
+        assert widths[i] == int(np.sum(rel[i - 1] > 1e-6))
+    assert min(widths) < 8                    # some column was locked before the end
+    np.testing.assert_allclose(r.X_all.T @ r.X_all, np.eye(8), atol=1e-10)
