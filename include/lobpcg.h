@@ -95,6 +95,7 @@ typedef struct {
     int cholqr_shifted;       /* iterations whose Cholesky QR needed the diagonal shift */
     long long mlp_fallbacks;  /* entries where the learned factor was not finite and
                                  the diagonal step was used alone                     */
+    int locked_max;           /* most columns soft-locked at once (lobpcg_set_soft_lock) */
 } lobpcg_info;
 
 /* Fill *o with the defaults: F32, GRAM_AUTO, FORMAT_AUTO, tile 64, kmax 16,
@@ -186,6 +187,43 @@ int lobpcg_precond_apply(lobpcg_ctx *ctx, const void *R, const double *theta, vo
 #define LOBPCG_FAULT_RR_DROP_P     8
 #define LOBPCG_FAULT_RR            16
 int lobpcg_set_test_faults(lobpcg_ctx *ctx, int mask, int iteration);
+
+/*
+ * lobpcg_set_cholqr_passes -- Cholesky QR passes per orthonormalisation of W
+ * in lobpcg_solve: 1 (default; Section 3.5) or 2 (CholeskyQR2, Fukaya et al.
+ * 2014: the second pass, on the already orthonormalised W, brings its
+ * orthogonality error from about eps cond(W)^2 to about eps; each pass keeps
+ * the shifted factorisation as its fallback).  Returns LOBPCG_EINVAL for
+ * other values.  Host-only; applies to the following solves.
+ */
+int lobpcg_set_cholqr_passes(lobpcg_ctx *ctx, int passes);
+
+/*
+ * lobpcg_set_soft_lock -- soft locking in lobpcg_solve (on = 1; default 0): a
+ * column whose relative residual was at or below tol at the last check is
+ * locked, i.e. its residual direction W_j and its P_j are left out of the
+ * Rayleigh-Ritz basis while X_j stays in it; a locked column is released
+ * when its residual rises above tol again.  Converged columns then stop
+ * feeding rounding noise into W and P (the FP32 recurrences of eqs.
+ * upd1-upd2 drift).  The blocks keep their width: the Cholesky QR treats a
+ * locked column as absent and the Rayleigh-Ritz step drops it from the
+ * pencil.  lobpcg_info.locked_max reports the most columns locked at once.
+ * Returns LOBPCG_EINVAL unless on is 0 or 1.
+ */
+int lobpcg_set_soft_lock(lobpcg_ctx *ctx, int on);
+
+/*
+ * lobpcg_cholqr -- Cholesky QR of a block in place (Section 3.5):
+ * B = W^T W (FP64 Gram), B = R^T R, W <- W R^{-1}; passes = 2 repeats it on the
+ * result (CholeskyQR2).  Each pass falls back to the shifted factorisation of
+ * the unit-diagonal-scaled Gram (shift 1e-12 in FP64, 1e-6 in FP32 contexts)
+ * when the plain one fails; *shifted (may be NULL) counts those passes.
+ *   W   device, n x k row-major in the context dtype, overwritten
+ * Returns LOBPCG_ENOTSPD when a pass fails even shifted (W then holds the
+ * last completed pass), LOBPCG_EINVAL for k outside [1, kmax] or passes not
+ * 1 or 2.  Synchronises the stream.
+ */
+int lobpcg_cholqr(lobpcg_ctx *ctx, void *W, int k, int passes, int *shifted, void *stream);
 
 /*
  * lobpcg_set_fom_steps -- FOM steps of LOBPCG_PRECOND_FOM, 1 <= m <= 8

@@ -45,7 +45,8 @@ class Info(ctypes.Structure):
                 ("timing", ctypes.c_int),
                 ("t_spmm", ctypes.c_double), ("t_precond_update", ctypes.c_double), ("t_gram", ctypes.c_double),
                 ("t_rr", ctypes.c_double), ("t_orth", ctypes.c_double), ("t_total", ctypes.c_double),
-                ("harvest", ctypes.c_void_p), ("cholqr_shifted", ctypes.c_int), ("mlp_fallbacks", ctypes.c_longlong)]
+                ("harvest", ctypes.c_void_p), ("cholqr_shifted", ctypes.c_int), ("mlp_fallbacks", ctypes.c_longlong),
+                ("locked_max", ctypes.c_int)]
 
 
 MLP_NIN, MLP_HID, MLP_NPARAM, MLP_NBLOB = 4, 64, 4545, 4553
@@ -120,6 +121,12 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_mlp_last_error.argtypes = [P]
     lib.lobpcg_set_mlp.restype = cint
     lib.lobpcg_set_mlp.argtypes = [P, P]
+    lib.lobpcg_set_cholqr_passes.restype = cint
+    lib.lobpcg_set_cholqr_passes.argtypes = [P, cint]
+    lib.lobpcg_set_soft_lock.restype = cint
+    lib.lobpcg_set_soft_lock.argtypes = [P, cint]
+    lib.lobpcg_cholqr.restype = cint
+    lib.lobpcg_cholqr.argtypes = [P, P, cint, cint, ctypes.POINTER(cint), P]
     lib.lobpcg_set_fom_steps.restype = cint
     lib.lobpcg_set_fom_steps.argtypes = [P, cint]
     lib.lobpcg_set_test_faults.restype = cint
@@ -197,6 +204,7 @@ class SolveResult:
     gamma: float
     cholqr_shifted: int = 0
     mlp_fallbacks: int = 0
+    locked_max: int = 0
     times: dict = field(default_factory=dict)
     theta_hist: Optional[np.ndarray] = None
     rel_hist: Optional[np.ndarray] = None
@@ -305,6 +313,22 @@ class Context:
                                        _dev_ptr(G, torch.float64, "G"), prec, _stream_ptr(stream)), "gram")
         return G
 
+    def set_cholqr_passes(self, passes: int):
+        """lobpcg_set_cholqr_passes: 1 (Cholesky QR) or 2 (CholeskyQR2) in solves."""
+        self._check(load().lobpcg_set_cholqr_passes(self._h, int(passes)), "set_cholqr_passes")
+
+    def set_soft_lock(self, on: bool):
+        """lobpcg_set_soft_lock: converged columns leave W and P in solves."""
+        self._check(load().lobpcg_set_soft_lock(self._h, int(bool(on))), "set_soft_lock")
+
+    def cholqr(self, W, passes=1, stream=None):
+        """lobpcg_cholqr: W <- its Cholesky QR factor Q, in place; returns the number of
+        shifted passes."""
+        sh = ctypes.c_int()
+        self._check(load().lobpcg_cholqr(self._h, _dev_ptr(W, self.torch_dtype, "W"), W.shape[1], int(passes),
+                                         ctypes.byref(sh), _stream_ptr(stream)), "cholqr")
+        return sh.value
+
     def set_fom_steps(self, m: int):
         """lobpcg_set_fom_steps: FOM steps of the block-diagonal preconditioner (1..8)."""
         self._check(load().lobpcg_set_fom_steps(self._h, int(m)), "set_fom_steps")
@@ -364,6 +388,7 @@ class Context:
                           p_dropped=info.p_dropped, cholqr_retries=info.cholqr_retries,
                           confirmations=info.confirmations, refreshes=info.refreshes, gamma=info.gamma,
                           cholqr_shifted=info.cholqr_shifted, mlp_fallbacks=info.mlp_fallbacks,
+                          locked_max=info.locked_max,
                           times=dict(spmm=info.t_spmm, precond_update=info.t_precond_update, gram=info.t_gram,
                                      rr=info.t_rr, orth=info.t_orth, total=info.t_total))
         if history:

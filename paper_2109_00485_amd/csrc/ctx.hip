@@ -227,6 +227,20 @@ extern "C" int lobpcg_set_test_faults(lobpcg_ctx *ctx, int mask, int iteration) 
     return LOBPCG_OK;
 }
 
+extern "C" int lobpcg_set_cholqr_passes(lobpcg_ctx *ctx, int passes) {
+    if (!ctx) return LOBPCG_EINVAL;
+    if (passes != 1 && passes != 2) return set_err(ctx, LOBPCG_EINVAL, "Cholesky QR passes %d not 1 or 2", passes);
+    ctx->cholqr_passes = passes;
+    return LOBPCG_OK;
+}
+
+extern "C" int lobpcg_set_soft_lock(lobpcg_ctx *ctx, int on) {
+    if (!ctx) return LOBPCG_EINVAL;
+    if (on != 0 && on != 1) return set_err(ctx, LOBPCG_EINVAL, "soft lock %d not 0 or 1", on);
+    ctx->soft_lock = on;
+    return LOBPCG_OK;
+}
+
 extern "C" int lobpcg_set_precond_offset(lobpcg_ctx *ctx, double c) {
     if (!ctx) return LOBPCG_EINVAL;
     if (!(c >= 0.0) || !(c <= 1e6)) return set_err(ctx, LOBPCG_EINVAL, "precond offset %g outside [0, 1e6]", c);

@@ -81,9 +81,15 @@ __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__rest
     __shared__ double sc[NMAX];
     const int t = threadIdx.x;
     if (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL)) return;
+    // soft-locked columns are absent: identity rows and columns (R^{-1} leaves them alone)
+    const int lock = flags[3];
+    auto entry = [&](int i, int j) -> double {
+        if (((lock >> i) | (lock >> j)) & 1) return i == j ? 1.0 : 0.0;
+        return 0.5 * (B[i * k + j] + B[j * k + i]);
+    };
     for (int e = t; e < k * k; e += LOBPCG_WAVE) {
         int i = e / k, j = e % k;
-        a[i * LD + j] = 0.5 * (B[i * k + j] + B[j * k + i]);
+        a[i * LD + j] = entry(i, j);
     }
     __syncthreads();
     if (t < k) {
@@ -104,7 +110,8 @@ __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__rest
         // shifted Cholesky QR: factor B' + shift I (B' has unit diagonal)
         for (int e = t; e < k * k; e += LOBPCG_WAVE) {
             int i = e / k, j = e % k;
-            a[i * LD + j] = 0.5 * (B[i * k + j] + B[j * k + i]) * sc[i] * sc[j] + (i == j ? shift : 0.0);
+            const bool locked = ((lock >> i) | (lock >> j)) & 1;
+            a[i * LD + j] = entry(i, j) * sc[i] * sc[j] + (i == j && !locked ? shift : 0.0);
         }
         __syncthreads();
         ok = chol_lower(a, k, tol) && !(force & FORCE_CHOLQR);
@@ -182,6 +189,8 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
     __shared__ int idx[NMAX];
     __shared__ double pr_c[NPAIR], pr_s[NPAIR];
     __shared__ short2 ptab[NMAX - 1][NPAIR];
+    __shared__ int act[NMAX];
+    __shared__ int nact;
     __shared__ double sh[RR_THREADS / LOBPCG_WAVE];
     __shared__ double Ys[NMAX * KM_CHOL];
     const int t = threadIdx.x;
@@ -190,22 +199,35 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
     int nblk = nblk_in;
     // a 16-column thread grid for the entry-wise loops (no integer division)
     const int tr = t / 16, tc = t % 16, TR = RR_THREADS / 16;
+    // soft-locked columns of W and P (bit j of flags[3]) are left out of the pencil
+    const int lock = flags[3];
     for (;;) {
-        const int N = nblk * k;
+        const int Nfull = nblk * k;
+        if (t == 0) {
+            int m = 0;
+            for (int i = 0; i < Nfull; ++i) {
+                const int col = i - k * ((i >= k) + (i >= 2 * k));
+                if (i < k || !((lock >> col) & 1)) act[m++] = i;
+            }
+            nact = m;
+        }
+        __syncthreads();
+        const int N = nact;
         // pencil from lower blocks; diagonal blocks symmetrised
         for (int a = tr; a < N; a += TR)
             for (int b = tc; b < N; b += 16) {
-                const int ba = (a >= k) + (a >= 2 * k), bb = (b >= k) + (b >= 2 * k);
+                const int ia = act[a], ib = act[b];
+                const int ba = (ia >= k) + (ia >= 2 * k), bb = (ib >= k) + (ib >= 2 * k);
                 double o, g;
                 if (ba > bb) {
-                    o = M[a * KB + b];
-                    g = M[a * KB + KA + b];
+                    o = M[ia * KB + ib];
+                    g = M[ia * KB + KA + ib];
                 } else if (ba < bb) {
-                    o = M[b * KB + a];
-                    g = M[b * KB + KA + a];
+                    o = M[ib * KB + ia];
+                    g = M[ib * KB + KA + ia];
                 } else {
-                    o = 0.5 * (M[a * KB + b] + M[b * KB + a]);
-                    g = 0.5 * (M[a * KB + KA + b] + M[b * KB + KA + a]);
+                    o = 0.5 * (M[ia * KB + ib] + M[ib * KB + ia]);
+                    g = 0.5 * (M[ia * KB + KA + ib] + M[ib * KB + KA + ia]);
                 }
                 O[a * LD + b] = o;
                 A[a * LD + b] = g;
@@ -431,7 +453,14 @@ __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, cons
                 __syncthreads();
             }
             for (int i = tr; i < N; i += TR)
-                for (int c = tc; c < k; c += 16) Cout[i * k + c] = sc[i] * Ys[i * KM_CHOL + c];
+                for (int c = tc; c < k; c += 16) Cout[act[i] * k + c] = sc[i] * Ys[i * KM_CHOL + c];
+            // left-out columns take no part in the update
+            if (N < Nfull)
+                for (int i = tr; i < Nfull; i += TR) {
+                    const int col = i - k * ((i >= k) + (i >= 2 * k));
+                    if (i >= k && ((lock >> col) & 1))
+                        for (int c = tc; c < k; c += 16) Cout[i * k + c] = 0.0;
+                }
             if (t < k) theta[t] = A[idx[t] * LD + idx[t]];
         }
         if (t == 0) flags[1] = nblk;

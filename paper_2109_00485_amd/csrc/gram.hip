@@ -39,10 +39,15 @@ __device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((
 enum Mode { M_F64 = 0, M_F32 = 1, M_BF16X3 = 2 };
 
 struct GramDev {
-    const void *a[3];
+    const void *a[4];
     const void *b[6];
     int na, nb, wa, wb;
     int64_t n;
+    // output placement: row of A-list column m, column of B-list column j (-1: not
+    // written) in a partial of out_rows x out_cols
+    short arow[64];
+    short bcol[96];
+    int out_rows, out_cols;
 };
 
 // per-lane column pointer for a 16-wide tile of a concatenated block list
@@ -52,7 +57,9 @@ __device__ inline const TI *col_ptr(const void *const *blocks, int nblocks, int 
     return (const TI *)blocks[m / w] + (m % w);
 }
 
-template <typename TI, int MODE, int MT, int NT>
+// SKIP: bit i * NT + j set = output tile (i, j) not computed (its blocks are
+// not needed by the caller)
+template <typename TI, int MODE, int MT, int NT, int SKIP = 0>
 __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, double *__restrict__ partial) {
     using Acc = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
     using AccS = typename std::conditional<MODE == M_F64, double, float>::type;
@@ -113,6 +120,7 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
             for (int i = 0; i < MT; ++i)
 #pragma unroll
                 for (int j = 0; j < NT; ++j) {
+                    if ((SKIP >> (i * NT + j)) & 1) continue;
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[i], b0[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[i], b1[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[i], b0[j], acc[i][j], 0, 0, 0);
@@ -124,6 +132,7 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
                 for (int i = 0; i < MT; ++i)
 #pragma unroll
                     for (int j = 0; j < NT; ++j) {
+                        if ((SKIP >> (i * NT + j)) & 1) continue;
                         if constexpr (MODE == M_F64)
                             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64((AccS)fa[t][i], (AccS)fb[t][j],
                                                                              acc[i][j], 0, 0, 0);
@@ -181,14 +190,18 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
         }
         __syncthreads();
     }
-    double *out = partial + (size_t)blockIdx.x * KA * KB;
+    double *out = partial + (size_t)blockIdx.x * g.out_rows * g.out_cols;
     for (int e = threadIdx.x; e < MT * NT * 4 * LOBPCG_WAVE; e += GRAM_THREADS) {
         int l = e % LOBPCG_WAVE, r = (e / LOBPCG_WAVE) % 4, tile = e / (4 * LOBPCG_WAVE);
         int i = tile / NT, j = tile % NT;
+        if ((SKIP >> tile) & 1) continue;
         // output rows of lane l: FP32 MFMA holds 4*(l/16)+r, FP64 MFMA holds (l/16)+4*r
         int m = MODE == M_F64 ? 16 * i + (l / 16) + 4 * r : 16 * i + 4 * (l / 16) + r;
         int nn = 16 * j + (l % 16);
-        if (m < KA && nn < KB) out[m * KB + nn] = red[e];
+        if (m < KA && nn < KB) {
+            const int om = g.arow[m], on = g.bcol[nn];
+            if (om >= 0 && on >= 0) out[om * g.out_cols + on] = red[e];
+        }
     }
 }
 
@@ -241,9 +254,13 @@ int launch_gram(lobpcg_ctx *ctx, const GramArgs &ga, int prec, double *out, hipS
     if (KA < 1 || KB < 1 || KA > 48 || KB > 96) return set_err(ctx, LOBPCG_EINVAL, "gram: %dx%d too large", KA, KB);
     const int MT = (KA + 15) / 16, NT = (KB + 15) / 16;
     GramDev g;
-    for (int i = 0; i < 3; ++i) g.a[i] = i < ga.na ? ga.a[i] : nullptr;
+    for (int i = 0; i < 4; ++i) g.a[i] = i < ga.na ? ga.a[i] : nullptr;
     for (int i = 0; i < 6; ++i) g.b[i] = i < ga.nb ? ga.b[i] : nullptr;
     g.na = ga.na; g.nb = ga.nb; g.wa = ga.wa; g.wb = ga.wb; g.n = ctx->n;
+    for (int m = 0; m < 64; ++m) g.arow[m] = m < KA ? m : -1;
+    for (int m = 0; m < 96; ++m) g.bcol[m] = m < KB ? m : -1;
+    g.out_rows = KA;
+    g.out_cols = KB;
     const int64_t nslab = (ctx->n + 15) / 16;
     // at least 4 slabs per wavefront (amortises the partial), at most one partial per slot
     const int grid = (int)std::min<int64_t>(ctx->gram_max_wg, std::max<int64_t>(1, (nslab + 4 * GRAM_WAVES - 1) / (4 * GRAM_WAVES)));
@@ -265,6 +282,50 @@ int launch_gram(lobpcg_ctx *ctx, const GramArgs &ga, int prec, double *out, hipS
     const int count = KA * KB;
     const int nstage = ceil_div(grid, RB);
     // stage-1 rows live after the partial slots (the allocation holds gram_max_wg / RB extra slots)
+    double *stage = ctx->gram_partial + (size_t)ctx->gram_max_wg * 48 * 96;
+    gram_reduce1_kernel<<<dim3(ceil_div(count, 64), nstage), 256, 0, s>>>(ctx->gram_partial, grid, count, stage);
+    gram_reduce2_kernel<<<ceil_div(count, 256), 256, 0, s>>>(stage, nstage, count, out);
+    return LOBPCG_OK;
+}
+
+// The Rayleigh-Ritz Gram [X W P]^T [X W P HX HW HP] for k = 8 reads only the
+// blocks of eq. Glower (the lower blocks and the diagonal blocks of both
+// matrices).  With the rows ordered [W P | X P] and the columns
+// [X HX | W HW | P HP], the 16 x 16 tiles ([W P], [P HP]) and ([X P], [W HW])
+// hold no needed block and are skipped: 4 tile products per 16-row slab
+// instead of 6.  The output keeps the layout of launch_gram (rows [X W P],
+// columns [X W P HX HW HP]); the blocks of the skipped tiles are not written.
+int launch_gram_rr8(lobpcg_ctx *ctx, const void *X, const void *W, const void *P, const void *HX,
+                    const void *HW, const void *HP, int prec, double *out, hipStream_t s) {
+    constexpr int k = 8;
+    GramDev g;
+    g.a[0] = W; g.a[1] = P; g.a[2] = X; g.a[3] = P;
+    g.b[0] = X; g.b[1] = HX; g.b[2] = W; g.b[3] = HW; g.b[4] = P; g.b[5] = HP;
+    g.na = 4; g.nb = 6; g.wa = g.wb = k; g.n = ctx->n;
+    const int arow_blk[4] = {1, 2, 0, 2};            // W P X P -> output row blocks
+    const int bcol_blk[6] = {0, 3, 1, 4, 2, 5};      // X HX W HW P HP -> output column blocks
+    for (int m = 0; m < 64; ++m) g.arow[m] = m < 4 * k ? (short)(arow_blk[m / k] * k + m % k) : -1;
+    for (int m = 0; m < 96; ++m) g.bcol[m] = m < 6 * k ? (short)(bcol_blk[m / k] * k + m % k) : -1;
+    g.out_rows = 3 * k;
+    g.out_cols = 6 * k;
+    const int64_t nslab = (ctx->n + 15) / 16;
+    const int grid = (int)std::min<int64_t>(ctx->gram_max_wg, std::max<int64_t>(1, (nslab + 4 * GRAM_WAVES - 1) / (4 * GRAM_WAVES)));
+    constexpr int SKIP = (1 << (0 * 3 + 2)) | (1 << (1 * 3 + 1));
+    if (prec == LOBPCG_GRAM_AUTO) prec = ctx->gram;
+    if (ctx->dtype == LOBPCG_F64) {
+        if (prec != LOBPCG_GRAM_F64) return set_err(ctx, LOBPCG_EINVAL, "gram: FP64 context needs GRAM_F64");
+        gram_partial_kernel<double, M_F64, 2, 3, SKIP><<<grid, GRAM_THREADS, 0, s>>>(g, ctx->gram_partial);
+    } else if (prec == LOBPCG_GRAM_F64) {
+        gram_partial_kernel<float, M_F64, 2, 3, SKIP><<<grid, GRAM_THREADS, 0, s>>>(g, ctx->gram_partial);
+    } else if (prec == LOBPCG_GRAM_F32) {
+        gram_partial_kernel<float, M_F32, 2, 3, SKIP><<<grid, GRAM_THREADS, 0, s>>>(g, ctx->gram_partial);
+    } else if (prec == LOBPCG_GRAM_BF16X3) {
+        gram_partial_kernel<float, M_BF16X3, 2, 3, SKIP><<<grid, GRAM_THREADS, 0, s>>>(g, ctx->gram_partial);
+    } else {
+        return set_err(ctx, LOBPCG_EINVAL, "gram: bad precision %d", prec);
+    }
+    const int count = 3 * k * 6 * k;
+    const int nstage = ceil_div(grid, RB);
     double *stage = ctx->gram_partial + (size_t)ctx->gram_max_wg * 48 * 96;
     gram_reduce1_kernel<<<dim3(ceil_div(count, 64), nstage), 256, 0, s>>>(ctx->gram_partial, grid, count, stage);
     gram_reduce2_kernel<<<ceil_div(count, 256), 256, 0, s>>>(stage, nstage, count, out);
@@ -343,7 +404,7 @@ extern "C" int lobpcg_gram_noalloc(const void *A, int ka, const void *B, int kb,
     int rc = scratch_for_current_device(&scr);
     if (rc != LOBPCG_OK) return rc;
     GramDev g;
-    for (int i = 0; i < 3; ++i) g.a[i] = nullptr;
+    for (int i = 0; i < 4; ++i) g.a[i] = nullptr;
     for (int i = 0; i < 6; ++i) g.b[i] = nullptr;
     g.a[0] = A;
     g.b[0] = B;
@@ -351,6 +412,10 @@ extern "C" int lobpcg_gram_noalloc(const void *A, int ka, const void *B, int kb,
     g.wa = ka;
     g.wb = kb;
     g.n = n;
+    for (int m = 0; m < 64; ++m) g.arow[m] = m < ka ? m : -1;
+    for (int m = 0; m < 96; ++m) g.bcol[m] = m < kb ? m : -1;
+    g.out_rows = ka;
+    g.out_cols = kb;
     const int MT = (ka + 15) / 16, NT = (kb + 15) / 16;
     const int64_t nslab = (n + 15) / 16;
     const int grid = (int)std::min<int64_t>(NOALLOC_MAX_WG, std::max<int64_t>(1, (nslab + 4 * GRAM_WAVES - 1) / (4 * GRAM_WAVES)));

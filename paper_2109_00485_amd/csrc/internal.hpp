@@ -101,6 +101,9 @@ struct lobpcg_ctx {
     int refresh_every = 0;  // explicit H X, H P recomputation period (0 = only on apparent convergence)
     // failure branches forced at one iteration (tests of the error paths)
     int test_fault_mask = 0, test_fault_iter = -1;
+    // Cholesky QR passes per orthonormalisation of W (2: CholeskyQR2) and soft locking
+    int cholqr_passes = 1;
+    int soft_lock = 0;
     unsigned long long *mlp_fallback_count = nullptr;   // device counter of per-entry MLP fallbacks
     // block-diagonal preconditioner: dense symmetric 64 x 64 diagonal tiles of H
     // (context dtype, [tile][64][64], unit diagonal past n) and its FOM step count
@@ -175,11 +178,17 @@ struct GramArgs {
     int na, nb, wa, wb;
 };
 int launch_gram(lobpcg_ctx *ctx, const GramArgs &g, int prec, double *out, hipStream_t s);
+// the Rayleigh-Ritz Gram of [X W P] for k = 8 with only eq. Glower's blocks computed
+int launch_gram_rr8(lobpcg_ctx *ctx, const void *X, const void *W, const void *P, const void *HX,
+                    const void *HW, const void *HP, int prec, double *out, hipStream_t s);
 
 // out = sum_b in_b * M_b  (M_b k x k FP64 row-major; NULL = identity; coef_b scales)
 int launch_combine(lobpcg_ctx *ctx, int k, int nin, const void *const *in, const double *const *mats,
                    const double *coef, void *out, hipStream_t s);
 
+// flags[3] holds the soft-lock mask (bit j: column j of W and P left out);
+// cholinv treats those columns as absent (identity), Rayleigh-Ritz drops them
+int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s, int force = 0, int lock = 0);
 int launch_cholinv(lobpcg_ctx *ctx, int k, const double *B, double *rinv, hipStream_t s);
 int launch_rr(lobpcg_ctx *ctx, int k, int nblk, hipStream_t s);
 int launch_update(lobpcg_ctx *ctx, int k, int nblk, int precond, int write_w, hipStream_t s);

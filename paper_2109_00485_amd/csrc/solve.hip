@@ -12,13 +12,13 @@
 // Convergence: rel_j = ||r_j|| / (max(|theta_j|, tau) ||x_j||) <= tol for the
 // nev wanted columns; then H X is recomputed explicitly, theta_j becomes the
 // Rayleigh quotient x_j^T H x_j / x_j^T x_j, and the test is repeated.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <vector>
 
 #include "internal.hpp"
 
-int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s, int force = 0);
 
 namespace {
 
@@ -77,7 +77,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     const bool timing = info && info->timing;
     Timer tm{ctx, s, timing};
     double t_spmm = 0, t_upd = 0, t_gram = 0, t_rr = 0, t_orth = 0;
-    int n_spmm = 0, p_dropped = 0, retries = 0, confirmations = 0, refreshes = 0, shifted = 0;
+    int n_spmm = 0, p_dropped = 0, retries = 0, confirmations = 0, refreshes = 0, shifted = 0, locked_max = 0;
     // failure branches forced from the host (lobpcg_set_test_faults): device bits
     // for attempt `attempt` of iteration `iter` (iteration 0: the initial Rayleigh-Ritz)
     auto forced = [&](int iter, int attempt) -> int {
@@ -98,6 +98,8 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
         return LOBPCG_OK;
     };
     auto gram_rr_input = [&](int nb) -> int {
+        if (k == 8 && nb == 3)
+            return launch_gram_rr8(ctx, ctx->X, ctx->W, ctx->P, ctx->HX, ctx->HW, ctx->HP, ctx->gram, ctx->gram_out, s);
         GramArgs g{};
         void *S[3] = {ctx->X, ctx->W, ctx->P};
         void *HS[3] = {ctx->HX, ctx->HW, ctx->HP};
@@ -179,9 +181,16 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
         }
         if (it >= maxiter) break;
         ++it;
+        // soft locking: the columns converged at this check leave W and P
+        int lock = 0;
+        if (ctx->soft_lock)
+            for (int j = 0; j < k; ++j)
+                if (rel[j] <= tol) lock |= 1 << j;
+        if (lock == (1 << k) - 1) lock = 0;   // (cannot happen: every column converged ends the solve)
+        locked_max = std::max(locked_max, __builtin_popcount(lock));
         bool done_iter = false, rr_failed = false;
         for (int attempt = 0; attempt < 2 && !done_iter && !rr_failed; ++attempt) {
-            TRY(launch_set_flags(ctx, 0, 0, s, forced(it, attempt)));
+            TRY(launch_set_flags(ctx, 0, 0, s, forced(it, attempt), lock));
             tm.mark(0);
             // W <- W - X (X^T W), then Cholesky QR
             {
@@ -199,6 +208,12 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
                 const double *mats1[1] = {ctx->orth_rinv};
                 const double coef1[1] = {1.0};
                 TRY(launch_combine(ctx, k, 1, in1, mats1, coef1, ctx->W, s));
+                if (ctx->cholqr_passes == 2) {
+                    // CholeskyQR2: a second Cholesky QR of the orthonormalised W
+                    TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
+                    TRY(launch_cholinv(ctx, k, ctx->gram_out2, ctx->orth_rinv, s));
+                    TRY(launch_combine(ctx, k, 1, in1, mats1, coef1, ctx->W, s));
+                }
             }
             tm.mark(1);
             TRY(launch_spmm(ctx, ctx->W, ctx->HW, k, s));
@@ -285,6 +300,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
         info->confirmations = confirmations;
         info->refreshes = refreshes;
         info->cholqr_shifted = shifted;
+        info->locked_max = locked_max;
         info->mlp_fallbacks = (long long)fallbacks;
         info->status = status;
         info->gamma = ctx->gamma;
@@ -297,4 +313,37 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
     }
     if (status == LOBPCG_ENOCONV) set_err(ctx, status, "not converged after %d iterations", it);
     return status;
+}
+
+// Cholesky QR of a caller's block in place (Section 3.5): B = W^T W, B = R^T R,
+// W <- W R^{-1}, once or twice; the shifted factorisation is the fallback of
+// each pass, as in the solve.
+extern "C" int lobpcg_cholqr(lobpcg_ctx *ctx, void *W, int k, int passes, int *shifted, void *stream) {
+    if (!ctx) return LOBPCG_EINVAL;
+    if (!W) return set_err(ctx, LOBPCG_EINVAL, "cholqr: null pointer");
+    if (k < 1 || k > ctx->kmax) return set_err(ctx, LOBPCG_EINVAL, "cholqr: k=%d outside [1,%d]", k, ctx->kmax);
+    if (passes != 1 && passes != 2) return set_err(ctx, LOBPCG_EINVAL, "cholqr: passes %d not 1 or 2", passes);
+    hipStream_t s = (hipStream_t)stream;
+    int nshift = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+        int rc = launch_set_flags(ctx, 0, 0, s, 0, 0);
+        if (rc != LOBPCG_OK) return rc;
+        GramArgs g{};
+        g.a[0] = W; g.b[0] = W; g.na = g.nb = 1; g.wa = g.wb = k;
+        if ((rc = launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s)) != LOBPCG_OK) return rc;
+        if ((rc = launch_cholinv(ctx, k, ctx->gram_out2, ctx->orth_rinv, s)) != LOBPCG_OK) return rc;
+        const void *in1[1] = {W};
+        const double *mats1[1] = {ctx->orth_rinv};
+        const double coef1[1] = {1.0};
+        if ((rc = launch_combine(ctx, k, 1, in1, mats1, coef1, W, s)) != LOBPCG_OK) return rc;
+        int fl = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(&fl, ctx->dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        if (fl & FLAG_CHOLQR_FAIL) return set_err(ctx, LOBPCG_ENOTSPD, "cholqr: W^T W not positive definite (pass %d)", pass + 1);
+        if (fl & FLAG_CHOLQR_SHIFT) ++nshift;
+    }
+    if (shifted) *shifted = nshift;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(ctx, LOBPCG_EHIP, "cholqr launch: %s", hipGetErrorString(e));
+    return LOBPCG_OK;
 }

@@ -271,16 +271,16 @@ __global__ __launch_bounds__(UPD_THREADS) void precond_kernel(int64_t n, int k, 
     }
 }
 
-__global__ void set_flags_kernel(int *flags, int f0, int f1, int f2) {
-    if (threadIdx.x == 0) { flags[0] = f0; flags[1] = f1; flags[2] = f2; }
+__global__ void set_flags_kernel(int *flags, int f0, int f1, int f2, int f3) {
+    if (threadIdx.x == 0) { flags[0] = f0; flags[1] = f1; flags[2] = f2; flags[3] = f3; }
 }
 
 int grid_rows(int64_t n, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + UPD_THREADS - 1) / UPD_THREADS)); }
 
 }  // namespace
 
-int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s, int force) {
-    set_flags_kernel<<<1, 64, 0, s>>>(ctx->dflags, f0, f1, force);
+int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s, int force, int lock) {
+    set_flags_kernel<<<1, 64, 0, s>>>(ctx->dflags, f0, f1, force, lock);
     return LOBPCG_OK;
 }
 
