@@ -96,11 +96,13 @@ def learned_vs_diag(args):
     for seed in range(a, b):
         A = W.make_matrix(meta.get("workload", "random_sym_2m"), seed=seed, n=meta.get("n"), f32=True)
         offset = float(meta.get("offset", 0.0))
-        r = train.compare(A, net, k=8, nev=5, tol=1e-6, offset=offset)
+        r = train.compare(A, net, k=8, nev=5, tol=1e-6, offset=offset, also_offset=args.offset)
         rows.append(dict(seed=seed, **{k_: {kk: v[kk] for kk in ("iters", "seconds", "status", "rel")}
                                          for k_, v in r.items()}))
         extra = f" | diag at theta_j {r['diag_theta']['iters']} it {r['diag_theta']['seconds']:.3f} s" \
             if "diag_theta" in r else ""
+        extra += f" | diag offset {args.offset} {r['diag_offset']['iters']} it {r['diag_offset']['seconds']:.3f} s" \
+            if "diag_offset" in r else ""
         log(f"learned vs diag, seed {seed}: diag {r['diag']['iters']} it {r['diag']['seconds']:.3f} s | "
             f"mlp {r['mlp']['iters']} it {r['mlp']['seconds']:.3f} s{extra}")
     mean = lambda key, f: float(np.mean([x[key][f] for x in rows])) if all(key in x for x in rows) else None
@@ -113,6 +115,10 @@ def learned_vs_diag(args):
         # the diagonal step with the shift at theta_j (offset 0), the plain baseline
         out.update(diag_theta_iters=mean("diag_theta", "iters"), diag_theta_seconds=round(mean("diag_theta", "seconds"), 4),
                    speedup_vs_diag_theta=round(mean("diag_theta", "seconds") / ms, 3) if ms > 0 else None)
+    if mean("diag_offset", "iters") is not None:
+        # the diagonal step with its shift held --offset Ritz-value spreads below theta_j
+        out.update(diag_offset=args.offset, diag_offset_iters=mean("diag_offset", "iters"),
+                   diag_offset_seconds=round(mean("diag_offset", "seconds"), 4))
     out["runs"] = rows
     return out
 
@@ -214,7 +220,7 @@ def main():
                     help="also solve with the diagonal shift this many Ritz-value spreads below theta_j (0: skip)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-diagonal preconditioner comparison")
-    ap.add_argument("--learned-seeds", default="1000:1006",
+    ap.add_argument("--learned-seeds", default="1000:1020",
                     help="evaluation matrices (seeds) of the learned-preconditioner workload")
     ap.add_argument("--fom-steps", type=lambda v: [int(x) for x in v.split(",") if x], default=[2],
                     help="FOM steps of the block-diagonal preconditioner runs (empty: skip them)")
@@ -428,6 +434,21 @@ def main():
                 log(f"FOM m={m} offset {off}: status {rf.status} iters {rf.iters} {solve_fom[-1]['seconds']} s")
         ctx.set_precond_offset(0.0)
         ctx.set_fom_steps(4)
+    # the FP32-robustness options: CholeskyQR2 for W, and soft locking
+    solve_options = []
+    for name, setter in (("cholqr2", lambda on: ctx.set_cholqr_passes(2 if on else 1)),
+                         ("soft_lock", lambda on: ctx.set_soft_lock(on))):
+        setter(True)
+        Xr = X0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rr_ = ctx.solve(Xr, args.nev, tol=args.tol, maxiter=args.maxiter)
+        torch.cuda.synchronize()
+        setter(False)
+        solve_options.append(dict(option=name, iters=rr_.iters, seconds=round(time.perf_counter() - t0, 4),
+                                  status=rr_.status, locked_max=rr_.locked_max,
+                                  evals=[float(x) for x in rr_.evals[:args.nev]]))
+        log(f"{name}: status {rr_.status} iters {rr_.iters} {solve_options[-1]['seconds']} s")
     # the iteration count from a random start depends on rounding (the shifted
     # diagonal preconditioner is nearly singular while theta is far above the
     # wanted eigenvalues): report solves from a few other Gaussian starts too
@@ -463,6 +484,7 @@ def main():
         "solve_offset": solve_offset,
         "solve_learned": solve_learned,
         "solve_fom": solve_fom,
+        "solve_options": solve_options,
         "fom_apply": fom_apply,
         "spmm_standalone_ms": round(spmm_ms, 4),
         "spmm_k16": spmm16,

@@ -19,6 +19,12 @@ same offset (Context.set_precond_offset).
 Command line (synthetic matrices of a named workload, weights written as
 JSON):  python -m paper_2109_00485_amd.train --workload random_sym_2m \
             --train-seeds 0:16 --eval-seeds 1000:1020 --out weights.json
+
+A harvest too large for one process can be split: ``--shard-out FILE``
+harvests the given training seeds and writes their samples to a compressed
+file (features in FP32; the diagonal step, correction, weight and X row
+rounded to BF16, which keeps FP32's range), and ``--shards A,B,...`` trains
+on such files instead of harvesting.
 """
 from __future__ import annotations
 
@@ -100,10 +106,12 @@ def fit(net: Mlp, batch, steps=1500, lr=3e-3, lr_end=3e-4, log_every=100):
     return losses
 
 
-def compare(A, net: Mlp, *, k=8, nev=5, tol=1e-6, maxiter=5000, x0_seed=1, f32=True, offset=0.0):
+def compare(A, net: Mlp, *, k=8, nev=5, tol=1e-6, maxiter=5000, x0_seed=1, f32=True, offset=0.0,
+            also_offset=None):
     """Diagonal vs learned preconditioner on one matrix: iterations, seconds, final
     residuals.  "diag" is the diagonal step the network was trained on (shift
-    offset ``offset``); with offset > 0, "diag_theta" is the shift at theta_j."""
+    offset ``offset``); with offset > 0, "diag_theta" is the shift at theta_j;
+    ``also_offset`` adds "diag_offset", the diagonal step with that offset."""
     import torch
     from synth import workloads as W
     ctx = Context.from_csr(A, dtype=F32 if f32 else F64)
@@ -114,6 +122,8 @@ def compare(A, net: Mlp, *, k=8, nev=5, tol=1e-6, maxiter=5000, x0_seed=1, f32=T
     runs = [("diag", PRECOND_DIAG, offset), ("mlp", PRECOND_MLP, offset)]
     if offset > 0:
         runs.append(("diag_theta", PRECOND_DIAG, 0.0))
+    if also_offset is not None:
+        runs.append(("diag_offset", PRECOND_DIAG, float(also_offset)))
     for name, pc, c in runs:
         ctx.set_precond_offset(c)
         X = X0.clone()
@@ -127,6 +137,42 @@ def compare(A, net: Mlp, *, k=8, nev=5, tol=1e-6, maxiter=5000, x0_seed=1, f32=T
     ctx.set_mlp(None)
     ctx.close()
     return out
+
+
+def _bf16_bits(x: np.ndarray) -> np.ndarray:
+    """FP32 -> BF16 bit patterns, round to nearest even (finite inputs)."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def _bf16_value(b: np.ndarray) -> np.ndarray:
+    return (b.astype(np.uint32) << 16).view(np.float32)
+
+
+def save_shard(path: str, batch, meta: dict):
+    feat, U, T, w, Xrow, goff = (t.cpu().numpy() for t in batch.t)
+    np.savez_compressed(path, feat=feat.astype(np.float32), U=_bf16_bits(U), T=_bf16_bits(T), w=_bf16_bits(w),
+                        Xrow=_bf16_bits(Xrow), group_off=goff.astype(np.int64),
+                        meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load_shards(paths):
+    """Concatenate shard files into one device batch (group offsets rebased)."""
+    import torch
+    from . import Batch
+    parts, metas, base = [], [], 0
+    for p in paths:
+        with np.load(p, allow_pickle=False) as z:
+            goff = z["group_off"]
+            parts.append((z["feat"], _bf16_value(z["U"]), _bf16_value(z["T"]), _bf16_value(z["w"]),
+                          _bf16_value(z["Xrow"]).reshape(z["Xrow"].shape), goff[:-1] + base))
+            base += int(goff[-1])
+            metas.append(json.loads(bytes(z["meta"]).decode()))
+    cat = [np.concatenate([q[i] for q in parts]) for i in range(6)]
+    cat[5] = np.concatenate([cat[5], [base]]).astype(np.int64)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in cat]
+    return Batch(*dev), metas
 
 
 def _seeds(spec: str):
@@ -151,27 +197,48 @@ def main(argv=None):
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--offset", type=float, default=0.0,
                     help="diagonal preconditioner shift offset, in Ritz-value spreads below theta_j")
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--shard-out", default=None, help="harvest only: write the samples to this file")
+    ap.add_argument("--shards", default=None, help="train on these sample files (comma-separated)")
+    ap.add_argument("--out", default=None)
     ap.add_argument("--report", default=None, help="JSON report of the evaluation")
     args = ap.parse_args(argv)
     import torch
     from synth import workloads as W
     torch.cuda.set_device(0)
-    dummy = torch.zeros((1, args.nev), dtype=torch.float64, device="cuda")
-    hb = HarvestBuffer(args.capacity, args.capacity // 16, args.k, dummy, args.nev, every=args.every, rows=args.rows)
     t_start = time.time()
     runs = []
-    for seed in _seeds(args.train_seeds):
-        t0 = time.time()
-        A = W.make_matrix(args.workload, seed=seed, n=args.n, f32=False)
-        info = harvest_matrix(A, hb, k=args.k, nev=args.nev, every=args.every, rows=args.rows, seed=seed,
-                              offset=args.offset)
-        runs.append(dict(seed=seed, **info))
-        _log(f"seed {seed}: {info} samples {hb.nsamples} ({time.time() - t0:.1f}s)")
-        if hb.full:
-            _log("harvest buffer full")
-            break
-    batch = hb.batch()
+    if args.shards:
+        batch, shard_meta = load_shards(args.shards.split(","))
+        runs = [r for m in shard_meta for r in m.get("runs", [])]
+        train_seeds = ",".join(m.get("train_seeds", "?") for m in shard_meta)
+        # the harvest settings come from the shards
+        args.every, args.rows = shard_meta[0].get("every", args.every), shard_meta[0].get("rows", args.rows)
+        nsamples, ngroups = batch.t[0].shape[0], batch.t[5].shape[0] - 1
+        _log(f"{len(shard_meta)} shards: {nsamples} samples, {ngroups} groups, {len(runs)} runs")
+    else:
+        dummy = torch.zeros((1, args.nev), dtype=torch.float64, device="cuda")
+        hb = HarvestBuffer(args.capacity, args.capacity // 16, args.k, dummy, args.nev, every=args.every,
+                           rows=args.rows)
+        for seed in _seeds(args.train_seeds):
+            t0 = time.time()
+            A = W.make_matrix(args.workload, seed=seed, n=args.n, f32=False)
+            info = harvest_matrix(A, hb, k=args.k, nev=args.nev, every=args.every, rows=args.rows, seed=seed,
+                                  offset=args.offset)
+            runs.append(dict(seed=seed, **info))
+            _log(f"seed {seed}: {info} samples {hb.nsamples} ({time.time() - t0:.1f}s)")
+            if hb.full:
+                raise RuntimeError("harvest buffer full: raise --capacity or lower --rows")
+        batch = hb.batch()
+        train_seeds, nsamples, ngroups = args.train_seeds, hb.nsamples, hb.ngroups
+        if args.shard_out:
+            save_shard(args.shard_out, batch, dict(workload=args.workload, n=args.n, train_seeds=args.train_seeds,
+                                                   offset=args.offset, every=args.every, rows=args.rows,
+                                                   runs=runs))
+            _log(f"wrote {nsamples} samples / {ngroups} groups to {args.shard_out} "
+                 f"({time.time() - t_start:.0f}s)")
+            return
+    if not args.out:
+        raise SystemExit("--out is required unless --shard-out is given")
     net = Mlp(init_params(args.init_seed))
     net.fit_standardizer(batch.t[0])
     torch.cuda.synchronize()
@@ -179,11 +246,11 @@ def main(argv=None):
     losses = fit(net, batch, steps=args.steps, lr=args.lr, lr_end=args.lr_end)
     torch.cuda.synchronize()
     t_train = time.time() - t0
-    _log(f"trained {args.steps} steps on {hb.nsamples} samples / {hb.ngroups} groups in {t_train:.1f}s: "
+    _log(f"trained {args.steps} steps on {nsamples} samples / {ngroups} groups in {t_train:.1f}s: "
          f"loss {losses[0]:.5f} -> {losses[-1]:.5f}")
-    meta = dict(workload=args.workload, n=args.n, train_seeds=args.train_seeds, offset=args.offset,
+    meta = dict(workload=args.workload, n=args.n, train_seeds=train_seeds, offset=args.offset,
                 every=args.every, rows=args.rows,
-                steps=args.steps, lr=args.lr, lr_end=args.lr_end, samples=hb.nsamples, groups=hb.ngroups,
+                steps=args.steps, lr=args.lr, lr_end=args.lr_end, samples=nsamples, groups=ngroups,
                 loss_first=losses[0], loss_last=losses[-1], train_seconds=t_train)
     blob = net.params()
     save_params(args.out, blob, meta)
