@@ -51,6 +51,8 @@ extern "C" {
 #define LOBPCG_GRAM_F64    1     /* inputs upcast to FP64, FP64 MFMA            */
 #define LOBPCG_GRAM_F32    2     /* FP32 MFMA, FP64 reduction across workgroups */
 #define LOBPCG_GRAM_BF16X3 3     /* split-BF16 (a0b0 + a0b1 + a1b0) MFMA, FP32 inputs */
+#define LOBPCG_GRAM_BF16X6 4     /* three-term split-BF16, the six products with i + j <= 2;
+                                    FP32 sums per 16 rows, FP64 across them; FP32 inputs */
 
 #define LOBPCG_PRECOND_NONE 0    /* K = I                                       */
 #define LOBPCG_PRECOND_DIAG 1    /* W_ij = R_ij / s(d_i - sigma_j), sigma_j = theta_j by default */
@@ -259,7 +261,7 @@ int lobpcg_set_precond_offset(lobpcg_ctx *ctx, double c);
  * Section 3.5), reduced across the whole column in FP64.
  *   A  device, n x ka row-major;  B device, n x kb row-major (may alias A)
  *   G  device, double[ka*kb], row-major ka x kb, overwritten
- *   1 <= ka, kb <= 48; prec is a LOBPCG_GRAM_* value (BF16X3 needs an F32 context)
+ *   1 <= ka, kb <= 48; prec is a LOBPCG_GRAM_* value (BF16X3 and BF16X6 need an F32 context)
  */
 int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B, int kb, double *G,
                 int prec, void *stream);
@@ -272,7 +274,7 @@ int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B, int kb, d
  *   A      device, n x ka row-major;  B device, n x kb row-major (may alias A)
  *   n      rows, >= 1;  dtype LOBPCG_F32 or LOBPCG_F64 (of A and B)
  *   G      device, double[ka*kb], row-major ka x kb, overwritten
- *   prec   a LOBPCG_GRAM_* value; AUTO means FP64 (BF16X3 and F32 need F32 data)
+ *   prec   a LOBPCG_GRAM_* value; AUTO means FP64 (BF16X3, BF16X6 and F32 need F32 data)
  * The partial sums live in one library-owned device array per GPU (4.8 MB,
  * held until the process ends), so 1 <= ka, kb <= 48 (LOBPCG_EUNSUPPORTED
  * beyond) and calls that overlap on one GPU race: serialise them (one stream,

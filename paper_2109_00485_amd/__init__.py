@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblobpcg.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, ENOCONV, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F64 = 1, 2
-GRAM_AUTO, GRAM_F64, GRAM_F32, GRAM_BF16X3 = 0, 1, 2, 3
+GRAM_AUTO, GRAM_F64, GRAM_F32, GRAM_BF16X3, GRAM_BF16X6 = 0, 1, 2, 3, 4
 PRECOND_NONE, PRECOND_DIAG, PRECOND_MLP, PRECOND_FOM = 0, 1, 2, 3
 FORMAT_AUTO, FORMAT_CSR, FORMAT_TILED = 0, 1, 2
 

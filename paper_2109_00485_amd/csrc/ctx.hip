@@ -259,8 +259,8 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
     if (!row_ptr || !col || !val) return LOBPCG_EINVAL;
     if (o.dtype != LOBPCG_F32 && o.dtype != LOBPCG_F64) return LOBPCG_EINVAL;
     if (o.kmax < 1 || o.kmax > 16) return LOBPCG_EINVAL;
-    if (o.gram < LOBPCG_GRAM_AUTO || o.gram > LOBPCG_GRAM_BF16X3) return LOBPCG_EINVAL;
-    if (o.gram == LOBPCG_GRAM_BF16X3 && o.dtype != LOBPCG_F32) return LOBPCG_EINVAL;
+    if (o.gram < LOBPCG_GRAM_AUTO || o.gram > LOBPCG_GRAM_BF16X6) return LOBPCG_EINVAL;
+    if ((o.gram == LOBPCG_GRAM_BF16X3 || o.gram == LOBPCG_GRAM_BF16X6) && o.dtype != LOBPCG_F32) return LOBPCG_EINVAL;
     if (o.format < LOBPCG_FORMAT_AUTO || o.format > LOBPCG_FORMAT_TILED) return LOBPCG_EINVAL;
     if (o.tile != 64) return LOBPCG_EUNSUPPORTED;
     if (!(o.tau_rel > 0) || !(o.eps_rel > 0)) return LOBPCG_EINVAL;

@@ -10,7 +10,10 @@
 //
 // Precisions: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32), and
 // split-BF16 "x3" for FP32 inputs: a = a0 + a1 with a0 = bf16(a),
-// a1 = bf16(a - a0), and a.b ~ a0.b0 + a0.b1 + a1.b0 (v_mfma_f32_16x16x16bf16_1k).
+// a1 = bf16(a - a0), and a.b ~ a0.b0 + a0.b1 + a1.b0 (v_mfma_f32_16x16x16bf16_1k);
+// "x6" splits into three terms (a2 = bf16(a - a0 - a1): 24 significant bits,
+// FP32's) and keeps the six products with i + j <= 2, summed per 16-row slab
+// in FP32 and across slabs in FP64.
 //
 // MFMA operand layout used (16x16xK, wave64): lane l supplies
 // A[i = l % 16][kk] and B[kk][j = l % 16] for the kk owned by lane group l / 16;
@@ -36,7 +39,7 @@ __device__ inline unsigned short bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
-enum Mode { M_F64 = 0, M_F32 = 1, M_BF16X3 = 2 };
+enum Mode { M_F64 = 0, M_F32 = 1, M_BF16X3 = 2, M_BF16X6 = 3 };
 
 struct GramDev {
     const void *a[4];
@@ -61,7 +64,7 @@ __device__ inline const TI *col_ptr(const void *const *blocks, int nblocks, int 
 // not needed by the caller)
 template <typename TI, int MODE, int MT, int NT, int SKIP = 0>
 __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, double *__restrict__ partial) {
-    using Acc = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
+    using Acc = typename std::conditional<MODE == M_F64 || MODE == M_BF16X6, f64x4, f32x4>::type;
     using AccS = typename std::conditional<MODE == M_F64, double, float>::type;
     const int lane = threadIdx.x % LOBPCG_WAVE;
     const int wave = threadIdx.x / LOBPCG_WAVE;
@@ -83,7 +86,9 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
 
     // the 4 rows of a 16-row slab this lane supplies: r0 + 4t + lg (K = 4 per
     // instruction, four instructions) or r0 + 4lg + t (BF16, K = 16)
-    auto row_of = [&](int64_t r0, int t) -> int64_t { return MODE == M_BF16X3 ? r0 + 4 * lg + t : r0 + 4 * t + lg; };
+    auto row_of = [&](int64_t r0, int t) -> int64_t {
+        return MODE == M_BF16X3 || MODE == M_BF16X6 ? r0 + 4 * lg + t : r0 + 4 * t + lg;
+    };
     auto load = [&](int64_t slab, TI (&fa)[4][MT], TI (&fb)[4][NT]) {
         const int64_t r0 = slab * 16;
 #pragma unroll
@@ -97,7 +102,41 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
         }
     };
     auto compute = [&](const TI (&fa)[4][MT], const TI (&fb)[4][NT]) {
-        if constexpr (MODE == M_BF16X3) {
+        if constexpr (MODE == M_BF16X6) {
+            s16x4 a0[MT], a1[MT], a2[MT], b0[NT], b1[NT], b2[NT];
+            // v = h0 + h1 + h2 (BF16 each, round to nearest even at every step)
+            auto split3 = [](float v, s16x4 &h0, s16x4 &h1, s16x4 &h2, int t) {
+                const unsigned short u0 = bf16_rne(v);
+                const float r1 = v - bf16_to_f32(u0);
+                const unsigned short u1 = bf16_rne(r1);
+                h0[t] = (short)u0;
+                h1[t] = (short)u1;
+                h2[t] = (short)bf16_rne(r1 - bf16_to_f32(u1));
+            };
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+#pragma unroll
+                for (int i = 0; i < MT; ++i) split3((float)fa[t][i], a0[i], a1[i], a2[i], t);
+#pragma unroll
+                for (int j = 0; j < NT; ++j) split3((float)fb[t][j], b0[j], b1[j], b2[j], t);
+            }
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    if ((SKIP >> (i * NT + j)) & 1) continue;
+                    // smallest terms first; this slab's sum in FP32, then into FP64
+                    f32x4 t4 = {0.0f, 0.0f, 0.0f, 0.0f};
+                    t4 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2[i], b0[j], t4, 0, 0, 0);
+                    t4 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[i], b1[j], t4, 0, 0, 0);
+                    t4 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[i], b2[j], t4, 0, 0, 0);
+                    t4 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[i], b0[j], t4, 0, 0, 0);
+                    t4 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[i], b1[j], t4, 0, 0, 0);
+                    t4 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[i], b0[j], t4, 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)t4[r];
+                }
+        } else if constexpr (MODE == M_BF16X3) {
             s16x4 a0[MT], a1[MT], b0[NT], b1[NT];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -275,6 +314,8 @@ int launch_gram(lobpcg_ctx *ctx, const GramArgs &ga, int prec, double *out, hipS
         rc = dispatch_tiles<float, M_F32>(MT, NT, grid, g, ctx->gram_partial, s);
     } else if (prec == LOBPCG_GRAM_BF16X3) {
         rc = dispatch_tiles<float, M_BF16X3>(MT, NT, grid, g, ctx->gram_partial, s);
+    } else if (prec == LOBPCG_GRAM_BF16X6) {
+        rc = dispatch_tiles<float, M_BF16X6>(MT, NT, grid, g, ctx->gram_partial, s);
     } else {
         return set_err(ctx, LOBPCG_EINVAL, "gram: bad precision %d", prec);
     }
@@ -321,6 +362,8 @@ int launch_gram_rr8(lobpcg_ctx *ctx, const void *X, const void *W, const void *P
         gram_partial_kernel<float, M_F32, 2, 3, SKIP><<<grid, GRAM_THREADS, 0, s>>>(g, ctx->gram_partial);
     } else if (prec == LOBPCG_GRAM_BF16X3) {
         gram_partial_kernel<float, M_BF16X3, 2, 3, SKIP><<<grid, GRAM_THREADS, 0, s>>>(g, ctx->gram_partial);
+    } else if (prec == LOBPCG_GRAM_BF16X6) {
+        gram_partial_kernel<float, M_BF16X6, 2, 3, SKIP><<<grid, GRAM_THREADS, 0, s>>>(g, ctx->gram_partial);
     } else {
         return set_err(ctx, LOBPCG_EINVAL, "gram: bad precision %d", prec);
     }
@@ -337,9 +380,9 @@ extern "C" int lobpcg_gram(lobpcg_ctx *ctx, const void *A, int ka, const void *B
     if (!ctx) return LOBPCG_EINVAL;
     if (!A || !B || !G) return set_err(ctx, LOBPCG_EINVAL, "gram: null pointer");
     if (ka < 1 || kb < 1 || ka > 48 || kb > 48) return set_err(ctx, LOBPCG_EINVAL, "gram: ka, kb must be in [1,48]");
-    if (prec < LOBPCG_GRAM_AUTO || prec > LOBPCG_GRAM_BF16X3) return set_err(ctx, LOBPCG_EINVAL, "gram: bad precision");
-    if (prec == LOBPCG_GRAM_BF16X3 && ctx->dtype != LOBPCG_F32)
-        return set_err(ctx, LOBPCG_EINVAL, "gram: BF16X3 needs an FP32 context");
+    if (prec < LOBPCG_GRAM_AUTO || prec > LOBPCG_GRAM_BF16X6) return set_err(ctx, LOBPCG_EINVAL, "gram: bad precision");
+    if ((prec == LOBPCG_GRAM_BF16X3 || prec == LOBPCG_GRAM_BF16X6) && ctx->dtype != LOBPCG_F32)
+        return set_err(ctx, LOBPCG_EINVAL, "gram: split-BF16 products need an FP32 context");
     if (ctx->dtype == LOBPCG_F64 && (prec == LOBPCG_GRAM_F32))
         return set_err(ctx, LOBPCG_EINVAL, "gram: FP32 Gram of FP64 blocks is not offered");
     GramArgs ga{};
@@ -397,7 +440,7 @@ extern "C" int lobpcg_gram_noalloc(const void *A, int ka, const void *B, int kb,
     if (ka < 1 || kb < 1) return LOBPCG_EINVAL;
     if (ka > NOALLOC_MAX_K || kb > NOALLOC_MAX_K) return LOBPCG_EUNSUPPORTED;   // beyond the static scratch
     if (dtype != LOBPCG_F32 && dtype != LOBPCG_F64) return LOBPCG_EINVAL;
-    if (prec < LOBPCG_GRAM_AUTO || prec > LOBPCG_GRAM_BF16X3) return LOBPCG_EINVAL;
+    if (prec < LOBPCG_GRAM_AUTO || prec > LOBPCG_GRAM_BF16X6) return LOBPCG_EINVAL;
     if (prec == LOBPCG_GRAM_AUTO) prec = LOBPCG_GRAM_F64;
     if (dtype == LOBPCG_F64 && prec != LOBPCG_GRAM_F64) return LOBPCG_EINVAL;
     double *scr = nullptr;
@@ -426,8 +469,10 @@ extern "C" int lobpcg_gram_noalloc(const void *A, int ka, const void *B, int kb,
         rc = dispatch_tiles<float, M_F64>(MT, NT, grid, g, scr, s);
     else if (prec == LOBPCG_GRAM_F32)
         rc = dispatch_tiles<float, M_F32>(MT, NT, grid, g, scr, s);
-    else
+    else if (prec == LOBPCG_GRAM_BF16X3)
         rc = dispatch_tiles<float, M_BF16X3>(MT, NT, grid, g, scr, s);
+    else
+        rc = dispatch_tiles<float, M_BF16X6>(MT, NT, grid, g, scr, s);
     if (rc != LOBPCG_OK) return rc;
     const int count = ka * kb;
     const int nstage = ceil_div(grid, RB);

@@ -200,6 +200,26 @@ def test_bf16x3_gram_solve():
     check_against_oracle(H, ref, r, X.cpu().numpy().astype(np.float64), True)
 
 
+def test_bf16x6_gram_solve():
+    """The three-term split-BF16 Gram (products to 2^-24, slab sums in FP32 and
+    FP64 across them) meets the plain 1e-6 residual tolerance and the
+    eigenvalue bar against the oracle."""
+    import paper_2109_00485_amd as L
+    A = W.make_matrix("random_sym_20k")
+    H, ref = oracle_solve("rs20k", A)
+    val = np.asarray(A.val, dtype=np.float32)
+
+    class _A:
+        pass
+    a = _A()
+    a.n, a.row_ptr, a.col, a.val = A.n, A.row_ptr, A.col, val
+    ctx = L.Context.from_csr(a, dtype=L.F32, gram=L.GRAM_BF16X6)
+    X = to_dev(W.initial_block(A.n, 8, seed=1), np.float32)
+    r = ctx.solve(X, 5, tol=1e-6, maxiter=5000)
+    assert r.status == 0, r.status
+    check_against_oracle(H, ref, r, X.cpu().numpy().astype(np.float64), True)
+
+
 def test_laplacian_closed_form():
     import paper_2109_00485_amd as L
     n = 300
