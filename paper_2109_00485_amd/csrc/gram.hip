@@ -182,34 +182,41 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
         }
     };
 
-    // software pipeline: the next slab's loads are in flight during this slab's MFMAs
+    // software pipeline: the loads of the next PF slabs are in flight during this
+    // slab's MFMAs (two for FP32 inputs: one slab of MFMAs is shorter than a
+    // memory round trip; FP64 inputs keep one, their registers would spill)
     const int64_t nslab = (g.n + 15) / 16;
     const int64_t wave_id = (int64_t)blockIdx.x * GRAM_WAVES + wave;
     const int64_t nwaves = (int64_t)gridDim.x * GRAM_WAVES;
-    TI ca[4][MT], cb[4][NT];
-    if (wave_id < nslab) load(wave_id, ca, cb);
-    for (int64_t slab = wave_id; slab < nslab; slab += nwaves) {
-        TI na[4][MT], nb[4][NT];
-        const int64_t nx = slab + nwaves;
-        if (nx < nslab) {
-            load(nx, na, nb);
+    constexpr int PF = sizeof(TI) == 4 ? 2 : 1;
+    TI qa[PF + 1][4][MT], qb[PF + 1][4][NT];
+    auto load_or_zero = [&](int64_t sl, TI (&fa)[4][MT], TI (&fb)[4][NT]) {
+        if (sl < nslab) {
+            load(sl, fa, fb);
         } else {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
 #pragma unroll
-                for (int i = 0; i < MT; ++i) na[t][i] = TI(0);
+                for (int i = 0; i < MT; ++i) fa[t][i] = TI(0);
 #pragma unroll
-                for (int j = 0; j < NT; ++j) nb[t][j] = TI(0);
+                for (int j = 0; j < NT; ++j) fb[t][j] = TI(0);
             }
         }
-        compute(ca, cb);
+    };
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+    for (int p = 0; p < PF; ++p) load_or_zero(wave_id + p * nwaves, qa[p], qb[p]);
+    for (int64_t slab = wave_id; slab < nslab; slab += nwaves) {
+        load_or_zero(slab + PF * nwaves, qa[PF], qb[PF]);
+        compute(qa[0], qb[0]);
 #pragma unroll
-            for (int i = 0; i < MT; ++i) ca[t][i] = na[t][i];
+        for (int p = 0; p < PF; ++p)
 #pragma unroll
-            for (int j = 0; j < NT; ++j) cb[t][j] = nb[t][j];
-        }
+            for (int t = 0; t < 4; ++t) {
+#pragma unroll
+                for (int i = 0; i < MT; ++i) qa[p][t][i] = qa[p + 1][t][i];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) qb[p][t][j] = qb[p + 1][t][j];
+            }
     }
 
     // sum the wavefronts of this workgroup in LDS (FP64), one wave at a time
