@@ -226,9 +226,13 @@ def main():
                     help="FOM steps of the block-diagonal preconditioner runs (empty: skip them)")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only time the sparse product (profiling runs); prints one JSON line")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="time the diagonal-step solves only (no other preconditioners, options or starts)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --spmm-only: also run a plain 2 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
+    if args.solve_only:
+        args.offset, args.no_learned, args.fom_steps, args.other_starts = 0.0, True, [], []
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU (there is no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
@@ -436,7 +440,7 @@ def main():
         ctx.set_fom_steps(4)
     # the FP32-robustness options: CholeskyQR2 for W, and soft locking
     solve_options = []
-    for name, setter in (("cholqr2", lambda on: ctx.set_cholqr_passes(2 if on else 1)),
+    for name, setter in [] if args.solve_only else (("cholqr2", lambda on: ctx.set_cholqr_passes(2 if on else 1)),
                          ("soft_lock", lambda on: ctx.set_soft_lock(on))):
         setter(True)
         Xr = X0.clone()
