@@ -335,7 +335,7 @@ extern "C" int lobpcg_create(lobpcg_ctx **out, int64_t n, const int64_t *row_ptr
          hipMalloc((void **)&ctx->gram_out2, 48 * 96 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->rr_C, 48 * 16 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->rr_theta, 16 * sizeof(double)) == hipSuccess &&
-         hipMalloc((void **)&ctx->orth_rinv, 16 * 16 * sizeof(double)) == hipSuccess &&
+         hipMalloc((void **)&ctx->orth_rinv, 2 * 16 * 16 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->norm_partial, (size_t)ctx->norm_max_wg * 3 * 16 * sizeof(double)) == hipSuccess &&
          hipMalloc((void **)&ctx->report_dev, sizeof(Report)) == hipSuccess &&
          hipMalloc((void **)&ctx->mlp_fallback_count, sizeof(unsigned long long)) == hipSuccess &&

@@ -75,16 +75,55 @@ __device__ bool chol_lower(double *a, int N, double tol) {
     return bad == 0;
 }
 
+// Cholesky QR factor R^{-1} of a block W (Section 3.5).
+//   FUSED = false: B is W^T W (k x k).
+//   FUSED = true:  B is the 2k x 2k Gram of [X W] and W is first projected,
+//     W' = W - X C with C = X^T W; the Gram of W' follows from B without
+//     another pass over the rows: W'^T W' = W^T W - C^T C - C^T C + C^T (X^T X) C
+//     (exact for any X).  The kernel also writes m2 = -C R^{-1}, so that one
+//     combine pass W <- W R^{-1} + X m2 gives the orthonormalised projection.
+// One wavefront.
+template <bool FUSED>
 __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__restrict__ B, double *__restrict__ rinv,
-                                                     int *__restrict__ flags, double tol, double shift) {
+                                                     double *__restrict__ m2, int *__restrict__ flags, double tol,
+                                                     double shift) {
     __shared__ double a[NMAX * LD];
     __shared__ double sc[NMAX];
+    __shared__ double cs[FUSED ? KM_CHOL * KM_CHOL : 1], ts[FUSED ? KM_CHOL * KM_CHOL : 1];
+    __shared__ double bp[FUSED ? KM_CHOL * KM_CHOL : 1];
     const int t = threadIdx.x;
     if (flags[0] & (FLAG_CHOLQR_FAIL | FLAG_RR_FAIL)) return;
+    const int k2 = 2 * k;
+    if constexpr (FUSED) {
+        for (int e = t; e < k2 * k2; e += LOBPCG_WAVE) a[(e / k2) * LD + e % k2] = B[e];
+        __syncthreads();
+        // C = X^T W (both off-diagonal blocks averaged), then T = (X^T X) C
+        for (int e = t; e < k * k; e += LOBPCG_WAVE) {
+            const int i = e / k, j = e % k;
+            cs[i * KM_CHOL + j] = 0.5 * (a[i * LD + k + j] + a[(k + j) * LD + i]);
+        }
+        __syncthreads();
+        for (int e = t; e < k * k; e += LOBPCG_WAVE) {
+            const int i = e / k, j = e % k;
+            double v = 0.0;
+            for (int p = 0; p < k; ++p) v += 0.5 * (a[i * LD + p] + a[p * LD + i]) * cs[p * KM_CHOL + j];
+            ts[i * KM_CHOL + j] = v;
+        }
+        __syncthreads();
+        // projected Gram: W^T W + sum_p C[p][i] (T[p][j] - 2 C[p][j])
+        for (int e = t; e < k * k; e += LOBPCG_WAVE) {
+            const int i = e / k, j = e % k;
+            double v = a[(k + i) * LD + k + j];
+            for (int p = 0; p < k; ++p) v += cs[p * KM_CHOL + i] * (ts[p * KM_CHOL + j] - 2.0 * cs[p * KM_CHOL + j]);
+            bp[i * KM_CHOL + j] = v;
+        }
+        __syncthreads();
+    }
     // soft-locked columns are absent: identity rows and columns (R^{-1} leaves them alone)
     const int lock = flags[3];
     auto entry = [&](int i, int j) -> double {
         if (((lock >> i) | (lock >> j)) & 1) return i == j ? 1.0 : 0.0;
+        if constexpr (FUSED) return 0.5 * (bp[i * KM_CHOL + j] + bp[j * KM_CHOL + i]);
         return 0.5 * (B[i * k + j] + B[j * k + i]);
     };
     for (int e = t; e < k * k; e += LOBPCG_WAVE) {
@@ -131,7 +170,20 @@ __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__rest
             for (int p = i + 1; p < k; ++p) v -= a[p * LD + i] * y[p * KM_CHOL + c];   // R'[i][p] = L[p][i]
             y[i * KM_CHOL + c] = v / a[i * LD + i];
         }
-        for (int i = 0; i < k; ++i) rinv[i * k + c] = sc[i] * y[i * KM_CHOL + c];
+        for (int i = 0; i < k; ++i) {
+            y[i * KM_CHOL + c] *= sc[i];
+            rinv[i * k + c] = y[i * KM_CHOL + c];
+        }
+    }
+    if constexpr (FUSED) {
+        __syncthreads();
+        // m2 = -C R^{-1}
+        for (int e = t; e < k * k; e += LOBPCG_WAVE) {
+            const int i = e / k, c = e % k;
+            double v = 0.0;
+            for (int p = 0; p < k; ++p) v += cs[i * KM_CHOL + p] * y[p * KM_CHOL + c];
+            m2[i * k + c] = -v;
+        }
     }
 }
 
@@ -478,7 +530,14 @@ __global__ void rayleigh_quotient_kernel(int k, const double *__restrict__ M, do
 
 int launch_cholinv(lobpcg_ctx *ctx, int k, const double *B, double *rinv, hipStream_t s) {
     const double shift = ctx->dtype == LOBPCG_F64 ? 1e-12 : 1e-6;
-    cholinv_kernel<<<1, 64, 0, s>>>(k, B, rinv, ctx->dflags, 1e-14, shift);
+    cholinv_kernel<false><<<1, 64, 0, s>>>(k, B, rinv, nullptr, ctx->dflags, 1e-14, shift);
+    return LOBPCG_OK;
+}
+
+int launch_cholinv_projected(lobpcg_ctx *ctx, int k, const double *B2, double *rinv, double *m2, hipStream_t s) {
+    if (k > KM_CHOL) return set_err(ctx, LOBPCG_EUNSUPPORTED, "cholqr: k=%d above %d", k, KM_CHOL);
+    const double shift = ctx->dtype == LOBPCG_F64 ? 1e-12 : 1e-6;
+    cholinv_kernel<true><<<1, 64, 0, s>>>(k, B2, rinv, m2, ctx->dflags, 1e-14, shift);
     return LOBPCG_OK;
 }
 

@@ -61,9 +61,11 @@ __device__ inline const TI *col_ptr(const void *const *blocks, int nblocks, int 
 }
 
 // SKIP: bit i * NT + j set = output tile (i, j) not computed (its blocks are
-// not needed by the caller)
-template <typename TI, int MODE, int MT, int NT, int SKIP = 0>
+// not needed by the caller).  SYM: the B list is the A list (MT == NT), whose
+// loaded values serve as both operands.
+template <typename TI, int MODE, int MT, int NT, int SKIP = 0, bool SYM = false>
 __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, double *__restrict__ partial) {
+    static_assert(!SYM || MT == NT, "a symmetric Gram has square tiles");
     using Acc = typename std::conditional<MODE == M_F64 || MODE == M_BF16X6, f64x4, f32x4>::type;
     using AccS = typename std::conditional<MODE == M_F64, double, float>::type;
     const int lane = threadIdx.x % LOBPCG_WAVE;
@@ -97,8 +99,10 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
             const bool in = r < g.n;
 #pragma unroll
             for (int i = 0; i < MT; ++i) fa[t][i] = (pa[i] && in) ? pa[i][r * g.wa] : TI(0);
+            if constexpr (!SYM) {
 #pragma unroll
-            for (int j = 0; j < NT; ++j) fb[t][j] = (pb[j] && in) ? pb[j][r * g.wb] : TI(0);
+                for (int j = 0; j < NT; ++j) fb[t][j] = (pb[j] && in) ? pb[j][r * g.wb] : TI(0);
+            }
         }
     };
     auto compute = [&](const TI (&fa)[4][MT], const TI (&fb)[4][NT]) {
@@ -183,12 +187,13 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
     };
 
     // software pipeline: the loads of the next PF slabs are in flight during this
-    // slab's MFMAs (two for FP32 inputs: one slab of MFMAs is shorter than a
-    // memory round trip; FP64 inputs keep one, their registers would spill)
+    // slab's MFMAs (FP32 inputs: two, four for a single 16 x 16 tile; one slab
+    // of MFMAs is shorter than a memory round trip; FP64 inputs keep one, their
+    // registers would spill)
     const int64_t nslab = (g.n + 15) / 16;
     const int64_t wave_id = (int64_t)blockIdx.x * GRAM_WAVES + wave;
     const int64_t nwaves = (int64_t)gridDim.x * GRAM_WAVES;
-    constexpr int PF = sizeof(TI) == 4 ? 2 : 1;
+    constexpr int PF = sizeof(TI) == 4 ? (MT * NT == 1 ? 4 : 2) : 1;
     TI qa[PF + 1][4][MT], qb[PF + 1][4][NT];
     auto load_or_zero = [&](int64_t sl, TI (&fa)[4][MT], TI (&fb)[4][NT]) {
         if (sl < nslab) {
@@ -198,8 +203,10 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
             for (int t = 0; t < 4; ++t) {
 #pragma unroll
                 for (int i = 0; i < MT; ++i) fa[t][i] = TI(0);
+                if constexpr (!SYM) {
 #pragma unroll
-                for (int j = 0; j < NT; ++j) fb[t][j] = TI(0);
+                    for (int j = 0; j < NT; ++j) fb[t][j] = TI(0);
+                }
             }
         }
     };
@@ -207,15 +214,20 @@ __global__ __launch_bounds__(GRAM_THREADS) void gram_partial_kernel(GramDev g, d
     for (int p = 0; p < PF; ++p) load_or_zero(wave_id + p * nwaves, qa[p], qb[p]);
     for (int64_t slab = wave_id; slab < nslab; slab += nwaves) {
         load_or_zero(slab + PF * nwaves, qa[PF], qb[PF]);
-        compute(qa[0], qb[0]);
+        if constexpr (SYM)
+            compute(qa[0], qa[0]);
+        else
+            compute(qa[0], qb[0]);
 #pragma unroll
         for (int p = 0; p < PF; ++p)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
 #pragma unroll
                 for (int i = 0; i < MT; ++i) qa[p][t][i] = qa[p + 1][t][i];
+                if constexpr (!SYM) {
 #pragma unroll
-                for (int j = 0; j < NT; ++j) qb[p][t][j] = qb[p + 1][t][j];
+                    for (int j = 0; j < NT; ++j) qb[p][t][j] = qb[p + 1][t][j];
+                }
             }
     }
 
@@ -281,6 +293,13 @@ __global__ void gram_reduce2_kernel(const double *__restrict__ stage, int nstage
 
 template <typename TI, int MODE>
 int dispatch_tiles(int MT, int NT, int grid, const GramDev &g, double *partial, hipStream_t s) {
+    // the same block list on both sides (a Gram of the form S^T S)
+    bool sym = MT == NT && g.na == g.nb && g.wa == g.wb;
+    for (int i = 0; sym && i < g.na; ++i) sym = g.a[i] == g.b[i];
+    if (sym) {
+        if (MT == 1) { gram_partial_kernel<TI, MODE, 1, 1, 0, true><<<grid, GRAM_THREADS, 0, s>>>(g, partial); return LOBPCG_OK; }
+        if (MT == 2) { gram_partial_kernel<TI, MODE, 2, 2, 0, true><<<grid, GRAM_THREADS, 0, s>>>(g, partial); return LOBPCG_OK; }
+    }
 #define GRAM_CASE(a, b)                                                                        \
     if (MT == a && NT == b) {                                                                  \
         gram_partial_kernel<TI, MODE, a, b><<<grid, GRAM_THREADS, 0, s>>>(g, partial);         \

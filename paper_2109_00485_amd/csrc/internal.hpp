@@ -132,7 +132,7 @@ struct lobpcg_ctx {
     // small dense FP64 state
     double *rr_C = nullptr;          // 48 x 16
     double *rr_theta = nullptr;      // 16
-    double *orth_rinv = nullptr;     // 16 x 16
+    double *orth_rinv = nullptr;     // 16 x 16 R^{-1}, then 16 x 16 for -(X^T W) R^{-1}
     double *norm_partial = nullptr;  // [norm_max_wg][3*16]
     int norm_max_wg = 0;
     Report *report_dev = nullptr;
@@ -190,6 +190,9 @@ int launch_combine(lobpcg_ctx *ctx, int k, int nin, const void *const *in, const
 // cholinv treats those columns as absent (identity), Rayleigh-Ritz drops them
 int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s, int force = 0, int lock = 0);
 int launch_cholinv(lobpcg_ctx *ctx, int k, const double *B, double *rinv, hipStream_t s);
+// the same for the projection of W against X: B2 is the 2k x 2k Gram of [X W];
+// writes R^{-1} of W - X (X^T W) and m2 = -(X^T W) R^{-1}
+int launch_cholinv_projected(lobpcg_ctx *ctx, int k, const double *B2, double *rinv, double *m2, hipStream_t s);
 int launch_rr(lobpcg_ctx *ctx, int k, int nblk, hipStream_t s);
 int launch_update(lobpcg_ctx *ctx, int k, int nblk, int precond, int write_w, hipStream_t s);
 int launch_residual(lobpcg_ctx *ctx, int k, int precond, const double *theta, int write_w, hipStream_t s);

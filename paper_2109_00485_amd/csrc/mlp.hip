@@ -137,7 +137,7 @@ __device__ inline float bounded_scale_fast(float o) {
 // factor is not finite gets the diagonal step alone (counted in *fallbacks
 // when that is given).  Inside a solve, flags stops the kernel when the
 // iteration's Cholesky QR or Rayleigh-Ritz failed (W then still holds the
-// projected block the retry starts from).
+// block the retry starts from).
 // KP > 0 fixes k at compile time (the sample -> (row, column) split is a shift).
 // The next step's inputs are loaded before this step's matrix-core work, so
 // every wave keeps one step of loads in flight.

@@ -195,19 +195,41 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
             // W <- W - X (X^T W), then Cholesky QR
             {
                 GramArgs g{};
-                g.a[0] = ctx->X; g.b[0] = ctx->W; g.na = g.nb = 1; g.wa = g.wb = k;
-                TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
-                const void *in[2] = {ctx->W, ctx->X};
-                const double *mats[2] = {nullptr, ctx->gram_out2};
-                const double coef[2] = {1.0, -1.0};
-                TRY(launch_combine(ctx, k, 2, in, mats, coef, ctx->W, s));
-                g.a[0] = ctx->W;
-                TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
-                TRY(launch_cholinv(ctx, k, ctx->gram_out2, ctx->orth_rinv, s));
                 const void *in1[1] = {ctx->W};
                 const double *mats1[1] = {ctx->orth_rinv};
                 const double coef1[1] = {1.0};
-                TRY(launch_combine(ctx, k, 1, in1, mats1, coef1, ctx->W, s));
+                if (attempt == 0) {
+                    // one pass over [X W] gives X^T W, X^T X and W^T W; the
+                    // projected block's Gram follows from them, and one
+                    // combine writes W R^{-1} - X (X^T W) R^{-1}
+                    g.a[0] = g.b[0] = ctx->X;
+                    g.a[1] = g.b[1] = ctx->W;
+                    g.na = g.nb = 2; g.wa = g.wb = k;
+                    TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
+                    double *m2 = ctx->orth_rinv + 16 * 16;
+                    TRY(launch_cholinv_projected(ctx, k, ctx->gram_out2, ctx->orth_rinv, m2, s));
+                    const void *in[2] = {ctx->W, ctx->X};
+                    const double *mats[2] = {ctx->orth_rinv, m2};
+                    const double coef[2] = {1.0, 1.0};
+                    TRY(launch_combine(ctx, k, 2, in, mats, coef, ctx->W, s));
+                } else {
+                    // the retry after a failed factorisation (W left as it was):
+                    // project twice, then Cholesky QR of the stored block
+                    g.a[0] = ctx->X; g.b[0] = ctx->W; g.na = g.nb = 1; g.wa = g.wb = k;
+                    const void *in[2] = {ctx->W, ctx->X};
+                    const double *mats[2] = {nullptr, ctx->gram_out2};
+                    const double coef[2] = {1.0, -1.0};
+                    for (int pass = 0; pass < 2; ++pass) {
+                        TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
+                        TRY(launch_combine(ctx, k, 2, in, mats, coef, ctx->W, s));
+                    }
+                    g.a[0] = ctx->W;
+                    TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
+                    TRY(launch_cholinv(ctx, k, ctx->gram_out2, ctx->orth_rinv, s));
+                    TRY(launch_combine(ctx, k, 1, in1, mats1, coef1, ctx->W, s));
+                }
+                g = GramArgs{};
+                g.a[0] = g.b[0] = ctx->W; g.na = g.nb = 1; g.wa = g.wb = k;
                 if (ctx->cholqr_passes == 2) {
                     // CholeskyQR2: a second Cholesky QR of the orthonormalised W
                     TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
