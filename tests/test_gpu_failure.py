@@ -177,14 +177,19 @@ def test_nonfinite_network_falls_back_to_diagonal():
     net = L.Mlp(net_blob(nan_output=True))
     ctx.set_mlp(net)
     X = to_dev(W.initial_block(A.n, 8, seed=1), np.float64)
-    rm = ctx.solve(X, 5, tol=1e-6, maxiter=3000, precond=L.PRECOND_MLP)
+    rm = ctx.solve(X, 5, tol=1e-6, maxiter=3000, precond=L.PRECOND_MLP, history=True)
     # every application of the network fell back on every entry
     assert rm.mlp_fallbacks == A.n * 8 * (1 + rm.iters + rm.cholqr_retries + rm.confirmations)
     X = to_dev(W.initial_block(A.n, 8, seed=1), np.float64)
-    rd = ctx.solve(X, 5, tol=1e-6, maxiter=3000, precond=L.PRECOND_DIAG)
+    rd = ctx.solve(X, 5, tol=1e-6, maxiter=3000, precond=L.PRECOND_DIAG, history=True)
     assert rd.mlp_fallbacks == 0
-    # so the learned solve is the diagonal one (up to the rounding of 1/s versus a division)
-    assert abs(rm.iters - rd.iters) <= 2
+    # so the learned solve is the diagonal one up to the rounding of 1/s versus a
+    # division: the same Ritz values through the first iterations, to the
+    # rounding the nearly singular step amplifies (1e-8 measured; the iteration
+    # counts themselves move by a few with any rounding change, the shift at
+    # theta_j making the preconditioner nearly singular)
+    np.testing.assert_allclose(rm.theta_hist[:10], rd.theta_hist[:10], rtol=1e-6)
+    assert abs(rm.iters - rd.iters) <= 0.1 * rd.iters, (rm.iters, rd.iters)
     for r in (rm, rd):
         assert np.all(np.abs(r.evals[:5] - lam) <= 1e-6 * np.maximum(np.abs(lam), tau))
 

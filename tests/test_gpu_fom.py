@@ -180,10 +180,9 @@ def test_fom_steps_validation_and_default():
 def test_fom_solve_against_oracle(f32):
     """LOBPCG with the block-diagonal FOM preconditioner (shift at theta_j,
     m = 2) on a 64-tiled matrix: the same eigenvalues as the oracle's LOBPCG
-    with the oracle's FOM preconditioner, and far fewer iterations than the
-    diagonal preconditioner at the same shift (FP64: about 205 against 440;
-    the iteration counts themselves depend on rounding and are printed, not
-    compared with the oracle's)."""
+    with the oracle's FOM preconditioner.  The iteration counts depend on
+    rounding (with the shift at theta_j the diagonal step is nearly singular)
+    and are printed, not compared; the next test compares them over starts."""
     import paper_2109_00485_amd as L
     A = MATRICES["tiled"](f32)
     H = oracle.SymMatrix.from_csr(A)
@@ -205,4 +204,23 @@ def test_fom_solve_against_oracle(f32):
     Xg = X.cpu().numpy().astype(np.float64)
     G = Xg.T @ Xg
     assert np.abs(G - np.eye(8)).max() < (2e-5 if f32 else 1e-10)
-    assert r.iters < 0.7 * r_diag.iters, (r.iters, r_diag.iters)
+
+
+def test_fom_fewer_iterations_over_starts():
+    """The FOM preconditioner against the diagonal step at the same shift
+    (theta_j, m = 2), FP64, from six Gaussian starts: fewer iterations on
+    average.  One start alone says little: with the shift at theta_j the
+    diagonal step is nearly singular and a single count moves by a factor of
+    up to 3 with the rounding of the trajectory."""
+    import paper_2109_00485_amd as L
+    A = MATRICES["tiled"](False)
+    ctx = upload(A, False)
+    ctx.set_fom_steps(2)
+    its = {"diag": [], "fom": []}
+    for seed in range(1, 7):
+        for name, pc in (("diag", L.PRECOND_DIAG), ("fom", L.PRECOND_FOM)):
+            r = ctx.solve(to_dev(W.initial_block(A.n, 8, seed=seed), np.float64), 5, maxiter=3000, precond=pc)
+            assert r.status == 0, (name, seed, r.status)
+            its[name].append(r.iters)
+    print("iterations", its)
+    assert np.mean(its["fom"]) < 0.8 * np.mean(its["diag"]), its
