@@ -200,8 +200,11 @@ __global__ __launch_bounds__(64) void cholinv_kernel(int k, const double *__rest
 // round number, so its loads of A, V and of the rotations are independent.
 constexpr int RR_THREADS = 256;
 constexpr int NPAIR = NMAX / 2;
-// Jacobi units per thread: A blocks (a <= b) and V blocks of the largest pencil
-constexpr int RR_UNITS = (NPAIR * (NPAIR + 1) / 2 + NPAIR * NPAIR + RR_THREADS - 1) / RR_THREADS;
+// Jacobi units per thread: A blocks (a <= b) and V blocks of a pencil of up to
+// 2 np indices; the kernel is compiled for 1 (up to 24 indices, the k = 8
+// pencils), 2 (32) and 4 (48) units per thread
+__host__ __device__ constexpr int rr_units(int np) { return (np * (np + 1) / 2 + np * np + RR_THREADS - 1) / RR_THREADS; }
+static_assert(rr_units(12) == 1 && rr_units(16) == 2 && rr_units(NPAIR) == 4, "Jacobi units per thread");
 
 __device__ inline double block_total(double v, double *sh) {
     v = wave_sum(v);
@@ -231,6 +234,7 @@ __device__ inline void rr_pair(int a, int r, int Ne, int &p, int &q) {
     q = x < y ? y : x;
 }
 
+template <int RR_UNITS>
 __global__ __launch_bounds__(RR_THREADS) void rr_kernel(int k, int nblk_in, const double *__restrict__ M,
                                                         double *__restrict__ Cout, double *__restrict__ theta,
                                                         int *__restrict__ flags, double tol) {
@@ -551,7 +555,13 @@ int launch_rr(lobpcg_ctx *ctx, int k, int nblk, hipStream_t s) {
     // instead.  FP32 blocks keep 1e-8: at 1e-7 their rounding alone trips the test
     // there and the iteration, without P, stalls
     const double tol = ctx->dtype == LOBPCG_F64 ? 1e-7 : 1e-8;
-    rr_kernel<<<1, RR_THREADS, 0, s>>>(k, nblk, ctx->gram_out, ctx->rr_C, ctx->rr_theta, ctx->dflags, tol);
+    const int N = nblk * k, np = (N + 1) / 2;
+    if (np <= 12)
+        rr_kernel<1><<<1, RR_THREADS, 0, s>>>(k, nblk, ctx->gram_out, ctx->rr_C, ctx->rr_theta, ctx->dflags, tol);
+    else if (np <= 16)
+        rr_kernel<2><<<1, RR_THREADS, 0, s>>>(k, nblk, ctx->gram_out, ctx->rr_C, ctx->rr_theta, ctx->dflags, tol);
+    else
+        rr_kernel<rr_units(NPAIR)><<<1, RR_THREADS, 0, s>>>(k, nblk, ctx->gram_out, ctx->rr_C, ctx->rr_theta, ctx->dflags, tol);
     return LOBPCG_OK;
 }
 
