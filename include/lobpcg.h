@@ -228,6 +228,24 @@ int lobpcg_set_soft_lock(lobpcg_ctx *ctx, int on);
 int lobpcg_cholqr(lobpcg_ctx *ctx, void *W, int k, int passes, int *shifted, void *stream);
 
 /*
+ * lobpcg_orthonormalize -- the orthogonalisation step of lobpcg_solve on a
+ * caller's blocks (Section 3.5; Algorithm 1 before the product H W):
+ * W <- W - X (X^T W), then one Cholesky QR of the result, W <- W R^{-1}.
+ * It takes one read of X and W: the Gram of [X W] gives C = X^T W, X^T X and
+ * W^T W, the projected block's Gram is W^T W - C^T C - C^T C + C^T (X^T X) C
+ * (exact for any X), and one pass writes W R^{-1} - X (C R^{-1}).  The
+ * plain factorisation falls back to the shifted one as in lobpcg_cholqr;
+ * *shifted (may be NULL) is set to 1 when it did.
+ *   X   device, n x k row-major in the context dtype (read only; need not be
+ *       orthonormal, the projection is the formula above)
+ *   W   device, n x k row-major, overwritten; must not alias X
+ * Returns LOBPCG_ENOTSPD when the projected Gram is not positive definite even
+ * shifted (W is then unchanged), LOBPCG_EINVAL for null pointers or k outside
+ * [1, kmax].  Synchronises the stream.
+ */
+int lobpcg_orthonormalize(lobpcg_ctx *ctx, const void *X, void *W, int k, int *shifted, void *stream);
+
+/*
  * lobpcg_set_fom_steps -- FOM steps of LOBPCG_PRECOND_FOM, 1 <= m <= 8
  * (default 4; the paper uses three to five).  That preconditioner is the
  * block-diagonal K of Section 3.4: K_t = H_tt - sigma_j I, H_tt the t-th

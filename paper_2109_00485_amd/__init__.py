@@ -127,6 +127,8 @@ def load(path: str = LIB_PATH):
     lib.lobpcg_set_soft_lock.argtypes = [P, cint]
     lib.lobpcg_cholqr.restype = cint
     lib.lobpcg_cholqr.argtypes = [P, P, cint, cint, ctypes.POINTER(cint), P]
+    lib.lobpcg_orthonormalize.restype = cint
+    lib.lobpcg_orthonormalize.argtypes = [P, P, P, cint, ctypes.POINTER(cint), P]
     lib.lobpcg_set_fom_steps.restype = cint
     lib.lobpcg_set_fom_steps.argtypes = [P, cint]
     lib.lobpcg_set_test_faults.restype = cint
@@ -327,6 +329,15 @@ class Context:
         sh = ctypes.c_int()
         self._check(load().lobpcg_cholqr(self._h, _dev_ptr(W, self.torch_dtype, "W"), W.shape[1], int(passes),
                                          ctypes.byref(sh), _stream_ptr(stream)), "cholqr")
+        return sh.value
+
+    def orthonormalize(self, X, W, stream=None):
+        """lobpcg_orthonormalize: W <- Cholesky QR of W - X (X^T W), in place; returns 1
+        when the shifted factorisation was used."""
+        sh = ctypes.c_int()
+        self._check(load().lobpcg_orthonormalize(self._h, _dev_ptr(X, self.torch_dtype, "X"),
+                                                 _dev_ptr(W, self.torch_dtype, "W"), W.shape[1],
+                                                 ctypes.byref(sh), _stream_ptr(stream)), "orthonormalize")
         return sh.value
 
     def set_fom_steps(self, m: int):

@@ -53,6 +53,27 @@ void rel_from_report(const lobpcg_ctx *ctx, int k, double tau, double *rel, bool
     }
 }
 
+// W <- W - X (X^T W), then one Cholesky QR of the result (Section 3.5), from
+// one Gram launch over [X W]: C = X^T W, X^T X and W^T W give the projected
+// block's Gram, and one combine writes W R^{-1} - X (C R^{-1}).  Sets the
+// device flags as the Cholesky QR does; the combine leaves W as it was when the
+// factorisation failed.
+int project_cholqr(lobpcg_ctx *ctx, const void *X, void *W, int k, hipStream_t s) {
+    GramArgs g{};
+    g.a[0] = g.b[0] = X;
+    g.a[1] = g.b[1] = W;
+    g.na = g.nb = 2;
+    g.wa = g.wb = k;
+    int rc = launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s);
+    if (rc != LOBPCG_OK) return rc;
+    double *m2 = ctx->orth_rinv + 16 * 16;
+    if ((rc = launch_cholinv_projected(ctx, k, ctx->gram_out2, ctx->orth_rinv, m2, s)) != LOBPCG_OK) return rc;
+    const void *in[2] = {W, X};
+    const double *mats[2] = {ctx->orth_rinv, m2};
+    const double coef[2] = {1.0, 1.0};
+    return launch_combine(ctx, k, 2, in, mats, coef, W, s);
+}
+
 }  // namespace
 
 extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double *evals, double *rel_out, double tol,
@@ -199,19 +220,7 @@ extern "C" int lobpcg_solve(lobpcg_ctx *ctx, int k, int nev, void *Xuser, double
                 const double *mats1[1] = {ctx->orth_rinv};
                 const double coef1[1] = {1.0};
                 if (attempt == 0) {
-                    // one pass over [X W] gives X^T W, X^T X and W^T W; the
-                    // projected block's Gram follows from them, and one
-                    // combine writes W R^{-1} - X (X^T W) R^{-1}
-                    g.a[0] = g.b[0] = ctx->X;
-                    g.a[1] = g.b[1] = ctx->W;
-                    g.na = g.nb = 2; g.wa = g.wb = k;
-                    TRY(launch_gram(ctx, g, ctx->gram, ctx->gram_out2, s));
-                    double *m2 = ctx->orth_rinv + 16 * 16;
-                    TRY(launch_cholinv_projected(ctx, k, ctx->gram_out2, ctx->orth_rinv, m2, s));
-                    const void *in[2] = {ctx->W, ctx->X};
-                    const double *mats[2] = {ctx->orth_rinv, m2};
-                    const double coef[2] = {1.0, 1.0};
-                    TRY(launch_combine(ctx, k, 2, in, mats, coef, ctx->W, s));
+                    TRY(project_cholqr(ctx, ctx->X, ctx->W, k, s));
                 } else {
                     // the retry after a failed factorisation (W left as it was):
                     // project twice, then Cholesky QR of the stored block
@@ -367,5 +376,22 @@ extern "C" int lobpcg_cholqr(lobpcg_ctx *ctx, void *W, int k, int passes, int *s
     if (shifted) *shifted = nshift;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_err(ctx, LOBPCG_EHIP, "cholqr launch: %s", hipGetErrorString(e));
+    return LOBPCG_OK;
+}
+
+// The orthogonalisation step of lobpcg_solve on a caller's blocks.
+extern "C" int lobpcg_orthonormalize(lobpcg_ctx *ctx, const void *X, void *W, int k, int *shifted, void *stream) {
+    if (!ctx) return LOBPCG_EINVAL;
+    if (!X || !W) return set_err(ctx, LOBPCG_EINVAL, "orthonormalize: null pointer");
+    if (k < 1 || k > ctx->kmax) return set_err(ctx, LOBPCG_EINVAL, "orthonormalize: k=%d outside [1,%d]", k, ctx->kmax);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = launch_set_flags(ctx, 0, 0, s, 0, 0);
+    if (rc == LOBPCG_OK) rc = project_cholqr(ctx, X, W, k, s);
+    if (rc != LOBPCG_OK) return rc;
+    int fl = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&fl, ctx->dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (shifted) *shifted = (fl & FLAG_CHOLQR_SHIFT) ? 1 : 0;
+    if (fl & FLAG_CHOLQR_FAIL) return set_err(ctx, LOBPCG_ENOTSPD, "orthonormalize: projected Gram not positive definite");
     return LOBPCG_OK;
 }

@@ -74,6 +74,8 @@ def test_entry_points_reject_null_context(lib):
     assert lib.lobpcg_last_error(None) == b"null context"
     lib.lobpcg_destroy(None)
     assert lib.lobpcg_set_precond_offset(None, 1.0) == L.EINVAL
+    assert lib.lobpcg_cholqr(None, fake, 8, 1, None, None) == L.EINVAL
+    assert lib.lobpcg_orthonormalize(None, fake, fake, 8, None, None) == L.EINVAL
 
 
 def test_bench_refuses_more_than_one_gpu():
