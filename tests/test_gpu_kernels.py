@@ -86,7 +86,7 @@ def test_spmm_integer_bitwise(k, fmt, hubs):
 
 def test_format_choice():
     """AUTO picks the tiled format when the stored entries fill the 64 x 64
-    tiles they touch densely enough (at least 8 entries per touched tile on
+    tiles they touch densely enough (at least 64 entries per touched tile on
     average), 32-bit CSR indices otherwise; a forced tiled format works on the
     sparse-tiled matrix too.  Both give the oracle's rows."""
     import paper_2109_00485_amd as L
