@@ -144,6 +144,33 @@ def test_gram_parity(ka, kb, prec):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("k", [5, 8, 16, 24])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x6", "f64ctx"])
+def test_gram_same_block_parity(k, prec):
+    """A^T A with the same block on both sides (the kernel loads it once and
+    uses it as both operands; one 16-column tile for k <= 16, two for k = 24)
+    against the FP64 product.  With one product per entry pair (FP64, FP32)
+    the result is exactly symmetric; the split-BF16 terms of (i, j) and (j, i)
+    are summed in different orders."""
+    import paper_2109_00485_amd as L
+    torch_cuda()
+    n = 4099
+    A = synth.random_sym(n, 2, seed=1)
+    f32 = prec != "f64ctx"
+    dt = np.float32 if f32 else np.float64
+    ctx = upload(A, f32)
+    a = synth.gaussian_block(n, k, seed=6).astype(dt)
+    p = {"f64": L.GRAM_F64, "f32": L.GRAM_F32, "bf16x6": L.GRAM_BF16X6, "f64ctx": L.GRAM_F64}[prec]
+    ad = to_dev(a, dt)
+    G = ctx.gram(ad, ad, prec=p).cpu().numpy()
+    ref = a.astype(np.float64).T @ a.astype(np.float64)
+    scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+    tol = {"f64": 1e-13, "f64ctx": 1e-13, "f32": 2e-6, "bf16x6": 2e-7}[prec]
+    assert np.max(np.abs(G - ref) / scale) <= tol
+    if prec != "bf16x6":
+        assert np.array_equal(G, G.T)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x6"])
 def test_gram_integer_exact(prec):
     import paper_2109_00485_amd as L
