@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import synth
+from synth import workloads as W
 from gpu_util import row_error, torch_cuda, to_dev, upload
 
 pytestmark = pytest.mark.gpu
@@ -93,6 +94,8 @@ def test_format_choice():
     torch = torch_cuda()
     A = synth.tiled(64 * 200, tile_draws=20, p=0.05, seed=3)
     assert upload(A, True).query()["format"] == L.FORMAT_TILED
+    # ~20 entries per touched tile: the CSR product is the faster one there
+    assert upload(W.make_matrix("random_sym_20k"), False).query()["format"] == L.FORMAT_CSR
     B = synth.random_sym(200_000, 50, seed=3, f32=True)   # ~1 entry per touched tile
     H = oracle.SymMatrix.from_csr(B)
     X = synth.gaussian_block(B.n, 8, seed=2).astype(np.float32)
