@@ -125,7 +125,7 @@ def learned_vs_diag(args):
 
 def host_info():
     """The host the CPU baseline ran on: model, logical CPUs, CPUs this process
-    may use, and RAM (from /proc; the box's own figures, not this build's)."""
+    may use, and RAM (read from /proc at run time)."""
     info = {"logical_cpus": os.cpu_count()}
     try:
         info["usable_cpus"] = len(os.sched_getaffinity(0))
