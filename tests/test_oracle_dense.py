@@ -148,3 +148,29 @@ def test_cholqr2_shifted_first_pass():
     assert np.abs(Q @ R - W).max() <= 1e-14 * np.abs(W).max()
     Q3, _ = cholqr(Q)
     assert np.abs(Q3.T @ Q3 - np.eye(8)).max() < 1e-14
+
+
+@pytest.mark.parametrize("orthonormal_x", [True, False])
+def test_projected_gram_from_one_gram_of_x_and_w(orthonormal_x):
+    """The identity the GPU's one-pass orthogonalisation uses (Section 3.5's
+    projection W - X (X^T W) followed by Cholesky QR): with C = X^T W,
+    (W - X C)^T (W - X C) = W^T W - C^T C - C^T C + C^T (X^T X) C for any X,
+    so the Gram of [X W] alone gives the projected block's Gram, and
+    W R^{-1} - X (C R^{-1}) is the oracle's Q of the projected block."""
+    rng = np.random.default_rng(11)
+    n, k = 300, 6
+    X = rng.standard_normal((n, k))
+    if orthonormal_x:
+        X, _ = np.linalg.qr(X)
+    W = rng.standard_normal((n, k)) + X @ (3.0 * rng.standard_normal((k, k)))
+    C = X.T @ W
+    Wp = W - X @ C
+    B_direct = Wp.T @ Wp
+    B_formula = W.T @ W - C.T @ C - C.T @ C + C.T @ (X.T @ X) @ C
+    scale = np.abs(W.T @ W).max() + np.abs(C.T @ (X.T @ X) @ C).max()
+    assert np.abs(B_direct - B_formula).max() <= 1e-12 * scale
+    Q, R = cholqr(Wp)
+    Rf = np.linalg.cholesky(0.5 * (B_formula + B_formula.T)).T
+    Q_formula = W @ np.linalg.inv(Rf) - X @ (C @ np.linalg.inv(Rf))
+    assert np.abs(Q - Q_formula).max() <= 1e-9
+    assert np.abs(Q.T @ Q - np.eye(k)).max() <= 1e-12
