@@ -36,6 +36,7 @@ typedef __attribute__((address_space(3))) void *lds_ptr;
 
 constexpr int TAB_BYTES = 144;   // 65 uint16 chunk offsets, padded to 16 bytes
 constexpr int CH = 4;            // entries per chunk
+constexpr int CPOL_NT = 2;       // cache-policy operand of global_load_lds: non-temporal
 #ifndef LOBPCG_TILE_TG
 #define LOBPCG_TILE_TG 4         // lanes per output row
 #endif
@@ -110,12 +111,14 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(TileWav
         }
     };
     auto stage = [&]() {
-        // matrix bytes of the window: 1 KB per wave-load, lanes past the end idle
+        // matrix bytes of the window: 1 KB per wave-load, lanes past the end idle;
+        // read once per product, so marked non-temporal (cache policy NT) to
+        // leave the caches to the X blocks, which other windows read again
         const int nwl = (int)((nnb + 1023) >> 10);
         for (int j = wave; j < nwl; j += NWAVE)
             if ((int64_t)j * 1024 + lane * 16 < nnb)
                 __builtin_amdgcn_global_load_lds((const void *)(data + nb0 + (int64_t)j * 1024 + lane * 16),
-                                                 (lds_ptr)(mb + j * 1024), 16, 0, 0);
+                                                 (lds_ptr)(mb + j * 1024), 16, 0, CPOL_NT);
         if constexpr (FULL) {
             // X blocks: U wave-loads of 64 lanes x 16 bytes per 64-row block
 #pragma unroll
