@@ -287,8 +287,33 @@ int launch_set_flags(lobpcg_ctx *ctx, int f0, int f1, hipStream_t s, int force, 
 // write_w: store the preconditioned residual into W.  nblk = 0 means "no
 // combination" (theta given in ctx->rr_theta); nblk > 0 reads the block count
 // chosen by the Rayleigh-Ritz kernel from the device flags.
+//
+// The grid is what the device holds at once (workgroups per CU at this
+// kernel's register use x CUs, capped by the partial-sum buffer): every
+// workgroup then strides over the rows from the start, with no second, partly
+// filled batch of workgroups at the end (tiled_2m, k = 8: 200 vs 211 us per
+// update and reduction with the 2048-workgroup grid).
+template <typename T, int KP>
+int update_grid(lobpcg_ctx *ctx) {
+    // the kernel's occupancy, queried once (the same on every device of one build)
+    static const int per_cu = [] {
+        int b = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, update_kernel<T, KP>, UPD_THREADS, 0) == hipSuccess ? b
+                                                                                                               : 0;
+    }();
+    int cus = 0;
+    if (per_cu <= 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+        cus <= 0)
+        return grid_rows(ctx->n, ctx->norm_max_wg);
+    return grid_rows(ctx->n, std::min(ctx->norm_max_wg, per_cu * cus));
+}
+
 int launch_update(lobpcg_ctx *ctx, int k, int nblk, int precond, int write_w, hipStream_t s) {
-    const int grid = grid_rows(ctx->n, ctx->norm_max_wg);
+    int grid;
+    if (ctx->dtype == LOBPCG_F32)
+        grid = k == 8 ? update_grid<float, 8>(ctx) : k == 16 ? update_grid<float, 16>(ctx) : update_grid<float, 0>(ctx);
+    else
+        grid = k == 8 ? update_grid<double, 8>(ctx) : k == 16 ? update_grid<double, 16>(ctx) : update_grid<double, 0>(ctx);
     const double eps = ctx->eps_rel * ctx->gamma;
     const int pk = precond == LOBPCG_PRECOND_DIAG ? LOBPCG_PRECOND_DIAG : LOBPCG_PRECOND_NONE;
 #define UPD_LAUNCH(T, KP)                                                                                        \
